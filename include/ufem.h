@@ -1,0 +1,177 @@
+/*
+ * ufem.h -- C ABI of the MI355X (gfx950) matrix-free unfitted DG operator.
+ *
+ * Operator: v = A u for the SIPG discretisation of the Poisson problem on a
+ * Cartesian background mesh cut by a level set (union of balls), with Nitsche
+ * terms on the embedded boundary and a face ghost penalty on the faces of cut
+ * cells (Bergbauer, Munch, Wall, Kronbichler, arXiv 2404.07911, Section 2.1
+ * bilinear forms of the CG and DG methods, Section 2.2 ghost penalty).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: UFEM_OK (0) or a negative error code; ufem_last_error()
+ *    returns a message for the calling thread.  No C++ exception crosses the
+ *    ABI.
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
+ *    memory of the device the operator was set up on.  The caller owns every
+ *    pointer it passes; the library owns what it allocates (released by the
+ *    matching destroy call).
+ *  - Vectors are cell-contiguous: active cells in background order
+ *    (b = ix + n iy + n^2 iz), (p+1)^dim values per cell, local index
+ *    l = i + k j + k^2 m with k = p + 1 (x fastest; Section 3.2, tensor-product
+ *    index of the sum-factorised evaluation).  The nodal basis is the Lagrange
+ *    basis on the Gauss-Lobatto points of each cell.
+ *  - Quadrature-point (kappa) vectors follow the layout of ufem_info.seg:
+ *    [inside-cell volume | cut-cell volume | structured SIPG faces |
+ *     cut SIPG faces | interface], each segment in active-cell resp. face
+ *    order (faces ordered by lower cell, then axis).
+ *  - Stream arguments are hipStream_t values passed as void* (NULL = the
+ *    default stream).  Calls that take a stream are asynchronous.
+ */
+#ifndef UFEM_H
+#define UFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  UFEM_OK = 0,
+  UFEM_EINVAL = -1,      /* bad argument (null, size, aliasing, range) */
+  UFEM_ENOMEM = -2,      /* host or device allocation failed */
+  UFEM_EHIP = -3,        /* HIP runtime error (message has the HIP string) */
+  UFEM_EUNSUPPORTED = -4,/* valid but unsupported configuration */
+  UFEM_ESTATE = -5       /* call out of order (e.g. kappa missing) */
+};
+
+/* Term mask bits: volume (Poisson) term, SIPG interior-face terms, Nitsche
+ * interface terms, face ghost penalty. */
+enum {
+  UFEM_TERM_VOLUME = 1,
+  UFEM_TERM_SIPG = 2,
+  UFEM_TERM_NITSCHE = 4,
+  UFEM_TERM_GHOST = 8,
+  UFEM_TERM_ALL = 15
+};
+
+/* Arithmetic of an apply: every input, table, quadrature datum and
+ * accumulation is in this precision. */
+enum { UFEM_F64 = 0, UFEM_F32 = 1 };
+
+typedef struct ufem_plan ufem_plan; /* host-side plan (no GPU) */
+typedef struct ufem_op ufem_op;     /* device-side operator */
+
+/* Problem description.  All pointers are host pointers read during
+ * ufem_plan_create only. */
+typedef struct {
+  int32_t dim;           /* 2 or 3 */
+  int32_t n;             /* background cells per direction, >= 2 */
+  double lo, hi;         /* background box [lo, hi]^dim */
+  int32_t degree;        /* polynomial degree p, 1..7 (3D), 1..7 (2D) */
+  int32_t q_cut;         /* Gauss points per 1D piece of the cut-cell, cut-face
+                            and interface rules; 0 selects p + 1 */
+  int32_t max_depth;     /* subdivision limit of the cut rules; < 0 selects 4 */
+  int32_t n_balls;       /* level set phi = min_i (|x - c_i| - r_i), >= 1 */
+  const double* centers; /* host, n_balls * dim, row-major */
+  const double* radii;   /* host, n_balls, > 0 */
+  double nitsche_factor; /* tau_D = nitsche_factor * p^2 (Section 2.1) */
+  double sipg_factor;    /* gamma = sipg_factor * p^2, SIPG penalty gamma/h */
+  double gp_gamma;       /* ghost penalty weight */
+  int32_t gp_jmin;       /* lowest normal-derivative order penalised, 0..p */
+  int32_t gp_flat;       /* 0: gamma_j = gp_gamma/(j!)^2, 1: gamma_j = gp_gamma */
+} ufem_problem;
+
+typedef struct {
+  int64_t n_background; /* n^dim */
+  int64_t n_active;     /* cells with DoFs: inside + cut */
+  int64_t n_inside;
+  int64_t n_cut;
+  int64_t n_dofs;       /* n_active * (p+1)^dim */
+  int64_t n_faces;      /* interior faces between active cells */
+  int64_t n_faces_str;  /* with structured SIPG quadrature */
+  int64_t n_faces_cut;  /* with dimension-reduction SIPG quadrature */
+  int64_t n_faces_gp;   /* with ghost penalty */
+  int64_t n_qp;         /* length of a kappa vector */
+  int64_t seg[6];       /* kappa segment offsets (see header comment) */
+  int64_t max_qp_cut_cell; /* largest cut-cell volume rule */
+  int64_t n_fallback;   /* sub-boxes that hit the subdivision limit */
+  double h;             /* background cell size */
+} ufem_info;
+
+/* Build the host plan: cell classes (inside / cut / outside by exact
+ * ball-versus-box distances), the face lists, the dimension-reduction
+ * quadrature of every cut cell, cut face and interface piece (Saye 2015, as
+ * cited in Sections 1 and 2.3), and the quadrature-point layout.  No GPU is
+ * touched.  Errors: EINVAL for out-of-range fields, EUNSUPPORTED when an
+ * active cell touches the background boundary. */
+int ufem_plan_create(const ufem_problem* prob, ufem_plan** out);
+int ufem_plan_destroy(ufem_plan* plan);
+int ufem_plan_info(const ufem_plan* plan, ufem_info* info);
+
+/* Plan export (host buffers sized from ufem_info).
+ *  cls:   int8[n_background], 0 inside, 1 cut, 2 outside.
+ *  faces: int32[n_faces * 5], rows (lower cell, upper cell, axis, kind, gp)
+ *         with background cell indices and kind 0 structured, 1 cut,
+ *         2 no SIPG term. */
+int ufem_plan_cells(const ufem_plan* plan, int8_t* cls);
+int ufem_plan_faces(const ufem_plan* plan, int32_t* faces);
+/* Quadrature-point data in kappa order: xyz = physical coordinates
+ * (double[n_qp * dim]), ref = reference coordinates in the owning cell
+ * (double[n_qp * dim]; faces use the lower cell, on its upper face), w =
+ * reference weights (double[n_qp]; physical weight = w * h^dim for volume
+ * points, w * h^(dim-1) for face and interface points), nrm = unit normals of
+ * interface points (double[n_qp * dim], zero elsewhere).  Any pointer may be
+ * NULL. */
+int ufem_plan_qp(const ufem_plan* plan, double* xyz, double* ref, double* w, double* nrm);
+
+/* Upload the plan to `device` and build the operator.  The plan may be
+ * destroyed afterwards.  Allocates all device memory the operator needs
+ * (max_device_bytes > 0 caps it; ENOMEM beyond).  Tables are stored for both
+ * precisions. */
+int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_device_bytes, ufem_op** out);
+int ufem_destroy(ufem_op* op);
+int ufem_info_op(const ufem_op* op, ufem_info* info);
+
+/* Select the terms of subsequent applies (default UFEM_TERM_ALL). */
+int ufem_set_terms(ufem_op* op, int32_t term_mask);
+
+/* Per-quadrature-point coefficient kappa (the variable coefficient of the
+ * volume, SIPG and Nitsche terms; the ghost penalty carries none).  kappa is a
+ * device pointer to n_qp values of the given precision, copied into the
+ * operator on `stream`; kappa == NULL returns to kappa = 1. */
+int ufem_set_kappa(ufem_op* op, int32_t precision, const void* kappa, void* stream);
+
+/* v := A u (overwrite).  u, v: device pointers to n_dofs values of
+ * `precision`; u must not overlap v (EINVAL).  Asynchronous on `stream`;
+ * allocates nothing. */
+int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* stream);
+
+/* Adjoint pass for L(kappa, u) with residual weight w:
+ *   ATw := A^T w  (the transposed evaluation, integration and evaluation
+ *                  swapped; A is symmetric so this equals A w),
+ *   dkappa[q] := a_q(w, u), the contribution of quadrature point q to
+ *                w^T A(kappa) u divided by kappa_q (dL/dkappa_q for
+ *                L = 0.5 |A u - b|^2 with w = A u - b).
+ * w, u, ATw: device, n_dofs; dkappa: device, n_qp, or NULL to skip.  ATw must
+ * not overlap w or u. */
+int ufem_apply_adjoint(ufem_op* op, int32_t precision, const void* w, const void* u, void* ATw,
+                       void* dkappa, void* stream);
+
+/* Device BLAS-1 of the solvers (float64 unless noted), asynchronous on
+ * `stream`.  Result scalars are written to device memory.
+ *   dot:    out[0] = sum x_i y_i (float64 accumulation for both precisions)
+ *   axpby:  y = a x + b y
+ *   cast:   y (precision_out) = x (precision_in) element-wise */
+int ufem_dot(int32_t precision, int64_t n, const void* x, const void* y, double* out, void* stream);
+int ufem_axpby(int32_t precision, int64_t n, double a, const void* x, double b, void* y, void* stream);
+int ufem_cast(int32_t precision_in, int32_t precision_out, int64_t n, const void* x, void* y, void* stream);
+
+/* Thread-local message of the last failing call (never NULL). */
+const char* ufem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UFEM_H */

@@ -1,0 +1,28 @@
+"""MI355X (gfx950) matrix-free unfitted DG operator.
+
+Hot path: v = A u for the SIPG discretisation of the Poisson problem on a
+level-set-cut Cartesian mesh (Bergbauer, Munch, Wall, Kronbichler, arXiv
+2404.07911), with hand-written HIP kernels behind the C ABI in include/ufem.h.
+
+Importing the package loads libufem.so and fails if it has not been built.
+"""
+from . import _lib
+from ._lib import F32, F64, TERM_ALL, TERM_GHOST, TERM_NITSCHE, TERM_SIPG, TERM_VOLUME, UfemError
+from .ufem import Operator, Plan, Problem, ufem_apply
+
+_lib.lib()  # fail loudly when the native library is missing
+
+__all__ = [
+    "Plan",
+    "Problem",
+    "Operator",
+    "ufem_apply",
+    "UfemError",
+    "F64",
+    "F32",
+    "TERM_ALL",
+    "TERM_VOLUME",
+    "TERM_SIPG",
+    "TERM_NITSCHE",
+    "TERM_GHOST",
+]

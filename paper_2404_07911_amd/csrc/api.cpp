@@ -1,0 +1,514 @@
+// C ABI of the operator library: plan creation (host), upload (setup),
+// apply / adjoint launches and the solver BLAS-1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "plan.hpp"
+#include "ufem.h"
+
+struct ufem_plan {
+  ufem::Plan P;
+};
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hipfail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return UFEM_EHIP;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+void fill_info(const ufem::Plan& P, ufem_info* I) {
+  std::memset(I, 0, sizeof(*I));
+  I->n_background = (int64_t)P.cls.size();
+  I->n_active = (int64_t)P.active.size();
+  I->n_inside = (int64_t)P.inside.size();
+  I->n_cut = (int64_t)P.cut.size();
+  I->n_dofs = P.n_dofs();
+  I->n_faces = (int64_t)P.faces.size();
+  I->n_faces_str = P.n_faces_str;
+  I->n_faces_cut = P.n_faces_cut;
+  I->n_faces_gp = P.n_faces_gp;
+  I->n_qp = P.seg[5];
+  for (int i = 0; i < 6; ++i) I->seg[i] = P.seg[i];
+  I->max_qp_cut_cell = P.max_qp_cut_cell;
+  I->n_fallback = P.n_fallback;
+  I->h = P.h;
+}
+
+// 1D tables in the TabOff layout (double; converted per precision)
+std::vector<double> make_tables(const ufem::Plan& P) {
+  const int K = P.k;
+  std::vector<double> t(ufem::TabOff::size(K), 0.0);
+  std::vector<double> gx, gw, xl, tmp;
+  ufem::gauss_legendre01(K, gx, gw);
+  ufem::gauss_lobatto01(K, xl);
+  for (int q = 0; q < K; ++q) {
+    ufem::lagrange_all(xl, gx[q], 0, tmp);
+    for (int i = 0; i < K; ++i) t[ufem::TabOff::S(K) + q * K + i] = tmp[i];
+    ufem::lagrange_all(gx, gx[q], 1, tmp);
+    for (int r = 0; r < K; ++r) t[ufem::TabOff::DG(K) + q * K + r] = tmp[K + r];
+    t[ufem::TabOff::W(K) + q] = gw[q];
+  }
+  ufem::lagrange_all(xl, 0.0, K - 1, tmp);
+  for (int j = 0; j < K; ++j)
+    for (int l = 0; l < K; ++l) t[ufem::TabOff::E0(K) + j * K + l] = tmp[j * K + l];
+  ufem::lagrange_all(xl, 1.0, K - 1, tmp);
+  for (int j = 0; j < K; ++j)
+    for (int l = 0; l < K; ++l) t[ufem::TabOff::E1(K) + j * K + l] = tmp[j * K + l];
+  for (int i = 0; i < K; ++i) {
+    t[ufem::TabOff::X(K) + i] = xl[i];
+    double den = 1.0;
+    for (int j = 0; j < K; ++j)
+      if (j != i) den *= xl[i] - xl[j];
+    t[ufem::TabOff::ID(K) + i] = 1.0 / den;
+    t[ufem::TabOff::GW(K) + i] = i <= P.p ? P.gp_w[i] : 0.0;
+  }
+  return t;
+}
+
+}  // namespace
+
+struct ufem_op {
+  ufem::Plan P;  // host copy (layout, counts)
+  int device = 0;
+  int32_t terms = UFEM_TERM_ALL;
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  int64_t max_bytes = 0;
+  // integer data
+  int32_t *inside = nullptr, *cut_order = nullptr, *cut_rank = nullptr, *nb = nullptr, *flags = nullptr,
+          *slot_face = nullptr, *face_qn = nullptr;
+  int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
+  // per-precision data
+  struct Prec {
+    void *vol_x = nullptr, *vol_w = nullptr, *surf_x = nullptr, *surf_w = nullptr, *surf_n = nullptr,
+         *fcut_x = nullptr, *fcut_w = nullptr, *tab = nullptr, *kappa = nullptr;
+    bool has_kappa = false;
+  } prec[2];
+
+  ~ufem_op() {
+    DeviceGuard g(device);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  int alloc(void** p, size_t n) {
+    if (n == 0) n = 8;
+    if (max_bytes > 0 && bytes + (int64_t)n > max_bytes)
+      return fail(UFEM_ENOMEM, "device memory cap exceeded (max_device_bytes)");
+    hipError_t e = hipMalloc(p, n);
+    if (e != hipSuccess) return hipfail(e, "hipMalloc");
+    allocs.push_back(*p);
+    bytes += (int64_t)n;
+    return UFEM_OK;
+  }
+  template <class V>
+  int upload(void** p, const V& host) {
+    size_t n = host.size() * sizeof(typename V::value_type);
+    int rc = alloc(p, n);
+    if (rc) return rc;
+    if (!host.empty()) {
+      hipError_t e = hipMemcpy(*p, host.data(), n, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hipfail(e, "hipMemcpy");
+    }
+    return UFEM_OK;
+  }
+  template <typename T>
+  int upload_prec(Prec& d, const std::vector<double>& tab);
+  template <typename T>
+  ufem::DevArgs<T> args(const Prec& d) const;
+};
+
+template <typename T>
+int ufem_op::upload_prec(Prec& d, const std::vector<double>& tab) {
+  const ufem::Plan& Q = P;
+  const int dim = Q.dim;
+  auto soa = [&](const std::vector<double>& aos, int comps) {
+    size_t n = comps ? aos.size() / comps : 0;
+    std::vector<T> out(aos.size());
+    for (size_t i = 0; i < n; ++i)
+      for (int c = 0; c < comps; ++c) out[c * n + i] = (T)aos[i * comps + c];
+    return out;
+  };
+  auto conv = [&](const std::vector<double>& v) {
+    std::vector<T> out(v.size());
+    for (size_t i = 0; i < v.size(); ++i) out[i] = (T)v[i];
+    return out;
+  };
+  int rc;
+  if ((rc = upload(&d.vol_x, soa(Q.vol_x, dim)))) return rc;
+  if ((rc = upload(&d.vol_w, conv(Q.vol_w)))) return rc;
+  if ((rc = upload(&d.surf_x, soa(Q.surf_x, dim)))) return rc;
+  if ((rc = upload(&d.surf_w, conv(Q.surf_w)))) return rc;
+  if ((rc = upload(&d.surf_n, soa(Q.surf_n, dim)))) return rc;
+  if ((rc = upload(&d.fcut_x, soa(Q.fcut_x, dim - 1)))) return rc;
+  if ((rc = upload(&d.fcut_w, conv(Q.fcut_w)))) return rc;
+  if ((rc = upload(&d.tab, conv(tab)))) return rc;
+  if ((rc = alloc(&d.kappa, sizeof(T) * (size_t)std::max<int64_t>(1, Q.seg[5])))) return rc;
+  return UFEM_OK;
+}
+
+template <typename T>
+ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
+  ufem::DevArgs<T> a{};
+  a.n_active = (int32_t)P.active.size();
+  a.n_inside = (int32_t)P.inside.size();
+  a.n_cut = (int32_t)P.cut.size();
+  a.inside = inside;
+  a.cut_order = cut_order;
+  a.cut_rank = cut_rank;
+  a.nb = nb;
+  a.flags = flags;
+  a.slot_face = slot_face;
+  a.face_qoff = face_qoff;
+  a.face_qn = face_qn;
+  a.vol_off = vol_off;
+  a.surf_off = surf_off;
+  a.vol_x = (const T*)d.vol_x;
+  a.vol_w = (const T*)d.vol_w;
+  a.surf_x = (const T*)d.surf_x;
+  a.surf_w = (const T*)d.surf_w;
+  a.surf_n = (const T*)d.surf_n;
+  a.fcut_x = (const T*)d.fcut_x;
+  a.fcut_w = (const T*)d.fcut_w;
+  a.n_vol = (int64_t)P.vol_w.size();
+  a.n_surf = (int64_t)P.surf_w.size();
+  a.n_fcut = (int64_t)P.fcut_w.size();
+  for (int i = 0; i < 6; ++i) a.seg[i] = P.seg[i];
+  a.tab = (const T*)d.tab;
+  a.kappa = d.has_kappa ? (const T*)d.kappa : nullptr;
+  a.hs = (T)std::pow(P.h, P.dim - 2);
+  a.tau = (T)P.tau;
+  a.gamma = (T)P.gamma;
+  a.terms = terms;
+  return a;
+}
+
+extern "C" {
+
+const char* ufem_last_error(void) { return g_err.c_str(); }
+
+int ufem_plan_create(const ufem_problem* prob, ufem_plan** out) {
+  if (!prob || !out) return fail(UFEM_EINVAL, "ufem_plan_create: null argument");
+  *out = nullptr;
+  try {
+    ufem_plan* p = new ufem_plan();
+    int code = UFEM_OK;
+    std::string msg = ufem::build_plan(*prob, p->P, &code);
+    if (code != UFEM_OK) {
+      delete p;
+      return fail(code, "ufem_plan_create: " + msg);
+    }
+    *out = p;
+    return UFEM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(UFEM_ENOMEM, "ufem_plan_create: host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(UFEM_EINVAL, std::string("ufem_plan_create: ") + e.what());
+  }
+}
+
+int ufem_plan_destroy(ufem_plan* plan) {
+  delete plan;
+  return UFEM_OK;
+}
+
+int ufem_plan_info(const ufem_plan* plan, ufem_info* info) {
+  if (!plan || !info) return fail(UFEM_EINVAL, "ufem_plan_info: null argument");
+  fill_info(plan->P, info);
+  return UFEM_OK;
+}
+
+int ufem_plan_cells(const ufem_plan* plan, int8_t* cls) {
+  if (!plan || !cls) return fail(UFEM_EINVAL, "ufem_plan_cells: null argument");
+  std::memcpy(cls, plan->P.cls.data(), plan->P.cls.size());
+  return UFEM_OK;
+}
+
+int ufem_plan_faces(const ufem_plan* plan, int32_t* faces) {
+  if (!plan || !faces) return fail(UFEM_EINVAL, "ufem_plan_faces: null argument");
+  size_t i = 0;
+  for (const ufem::Face& f : plan->P.faces) {
+    faces[i++] = f.bm;
+    faces[i++] = f.bp;
+    faces[i++] = f.axis;
+    faces[i++] = f.kind;
+    faces[i++] = f.gp;
+  }
+  return UFEM_OK;
+}
+
+int ufem_plan_qp(const ufem_plan* plan, double* xyz, double* ref, double* w, double* nrm) {
+  if (!plan) return fail(UFEM_EINVAL, "ufem_plan_qp: null plan");
+  const ufem::Plan& P = plan->P;
+  const int dim = P.dim, K = P.k;
+  std::vector<double> gx, gw;
+  ufem::gauss_legendre01(K, gx, gw);
+  auto put = [&](int64_t q, const double* lo, const double* r, double wt, const double* n) {
+    for (int a = 0; a < dim; ++a) {
+      if (xyz) xyz[q * dim + a] = lo[a] + P.h * r[a];
+      if (ref) ref[q * dim + a] = r[a];
+      if (nrm) nrm[q * dim + a] = n ? n[a] : 0.0;
+    }
+    if (w) w[q] = wt;
+  };
+  const int nd = P.nd(), nf = P.nf();
+  int64_t q = 0;
+  double lo[3], r[3];
+  for (int32_t ar : P.inside) {
+    P.cell_lo(P.active[ar], lo);
+    for (int l = 0; l < nd; ++l, ++q) {
+      int rem = l;
+      double wt = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        int g = rem % K;
+        rem /= K;
+        r[a] = gx[g];
+        wt *= gw[g];
+      }
+      put(q, lo, r, wt, nullptr);
+    }
+  }
+  for (size_t i = 0; i < P.cut.size(); ++i) {
+    P.cell_lo(P.active[P.cut[i]], lo);
+    for (int64_t j = P.vol_off[i]; j < P.vol_off[i + 1]; ++j, ++q) put(q, lo, &P.vol_x[j * dim], P.vol_w[j], nullptr);
+  }
+  for (const ufem::Face& f : P.faces) {
+    if (f.kind != ufem::kFaceStructured) continue;
+    P.cell_lo(f.bm, lo);
+    for (int l = 0; l < nf; ++l, ++q) {
+      int rem = l;
+      double wt = 1.0;
+      for (int a = 0; a < dim; ++a) {
+        if (a == f.axis) { r[a] = 1.0; continue; }
+        int g = rem % K;
+        rem /= K;
+        r[a] = gx[g];
+        wt *= gw[g];
+      }
+      put(q, lo, r, wt, nullptr);
+    }
+  }
+  for (size_t i = 0; i + 1 < P.fcut_off.size(); ++i) {
+    const ufem::Face& f = P.faces[P.fcut_face[i]];
+    P.cell_lo(f.bm, lo);
+    for (int64_t j = P.fcut_off[i]; j < P.fcut_off[i + 1]; ++j, ++q) {
+      int c = 0;
+      for (int a = 0; a < dim; ++a) r[a] = a == f.axis ? 1.0 : P.fcut_x[j * (dim - 1) + c++];
+      put(q, lo, r, P.fcut_w[j], nullptr);
+    }
+  }
+  for (size_t i = 0; i < P.cut.size(); ++i) {
+    P.cell_lo(P.active[P.cut[i]], lo);
+    for (int64_t j = P.surf_off[i]; j < P.surf_off[i + 1]; ++j, ++q)
+      put(q, lo, &P.surf_x[j * dim], P.surf_w[j], &P.surf_n[j * dim]);
+  }
+  return UFEM_OK;
+}
+
+int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_device_bytes, ufem_op** out) {
+  (void)stream;
+  if (!plan || !out) return fail(UFEM_EINVAL, "ufem_setup: null argument");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hipfail(e, "ufem_setup: hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(UFEM_EINVAL, "ufem_setup: no such device");
+  DeviceGuard guard(device);
+  if (!guard.ok) return fail(UFEM_EHIP, "ufem_setup: hipSetDevice failed");
+  ufem_op* op = nullptr;
+  try {
+    op = new ufem_op();
+    op->P = plan->P;
+    op->device = device;
+    op->max_bytes = max_device_bytes;
+    const ufem::Plan& P = op->P;
+    const int dim = P.dim, S = 2 * dim;
+    const size_t na = P.active.size();
+    // neighbour ranks and flags per active cell and slot
+    std::vector<int32_t> nb(na * S, -1), flags(na, 0), slot_face(P.slot_face);
+    for (size_t r = 0; r < na; ++r) {
+      for (int s = 0; s < S; ++s) {
+        int32_t fi = P.slot_face[r * S + s];
+        if (fi < 0) continue;
+        const ufem::Face& f = P.faces[fi];
+        nb[r * S + s] = P.rank[(s & 1) ? f.bp : f.bm];
+        if (f.gp) flags[r] |= 1 << (ufem::kFlagGP + s);
+        if (f.kind == ufem::kFaceStructured) flags[r] |= 1 << (ufem::kFlagStr + s);
+        if (f.kind == ufem::kFaceCut) flags[r] |= 1 << (ufem::kFlagCut + s);
+      }
+    }
+    std::vector<int64_t> face_qoff(P.faces.size());
+    std::vector<int32_t> face_qn(P.faces.size());
+    for (size_t i = 0; i < P.faces.size(); ++i) {
+      face_qoff[i] = P.faces[i].qp_off;
+      face_qn[i] = P.faces[i].qp_n;
+    }
+    // cut cells processed in decreasing order of quadrature work
+    std::vector<int32_t> order(P.cut.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<int64_t> cost(P.cut.size());
+    for (size_t i = 0; i < P.cut.size(); ++i) {
+      int64_t c = (P.vol_off[i + 1] - P.vol_off[i]) + (P.surf_off[i + 1] - P.surf_off[i]);
+      for (int s = 0; s < S; ++s) {
+        int32_t fi = P.slot_face[(size_t)P.cut[i] * S + s];
+        if (fi >= 0) c += P.nf() + P.faces[fi].qp_n;
+      }
+      cost[i] = c;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+    int rc;
+    if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->cut_order, order)) ||
+        (rc = op->upload((void**)&op->cut_rank, P.cut)) || (rc = op->upload((void**)&op->nb, nb)) ||
+        (rc = op->upload((void**)&op->flags, flags)) || (rc = op->upload((void**)&op->slot_face, slot_face)) ||
+        (rc = op->upload((void**)&op->face_qoff, face_qoff)) || (rc = op->upload((void**)&op->face_qn, face_qn)) ||
+        (rc = op->upload((void**)&op->vol_off, P.vol_off)) || (rc = op->upload((void**)&op->surf_off, P.surf_off))) {
+      delete op;
+      return rc;
+    }
+    std::vector<double> tab = make_tables(P);
+    if ((rc = op->upload_prec<double>(op->prec[0], tab)) || (rc = op->upload_prec<float>(op->prec[1], tab))) {
+      delete op;
+      return rc;
+    }
+    *out = op;
+    return UFEM_OK;
+  } catch (const std::bad_alloc&) {
+    delete op;
+    return fail(UFEM_ENOMEM, "ufem_setup: host allocation failed");
+  }
+}
+
+int ufem_destroy(ufem_op* op) {
+  delete op;
+  return UFEM_OK;
+}
+
+int ufem_info_op(const ufem_op* op, ufem_info* info) {
+  if (!op || !info) return fail(UFEM_EINVAL, "ufem_info_op: null argument");
+  fill_info(op->P, info);
+  return UFEM_OK;
+}
+
+int ufem_set_terms(ufem_op* op, int32_t mask) {
+  if (!op) return fail(UFEM_EINVAL, "ufem_set_terms: null op");
+  if (mask < 0 || mask > UFEM_TERM_ALL) return fail(UFEM_EINVAL, "ufem_set_terms: bad mask");
+  op->terms = mask;
+  return UFEM_OK;
+}
+
+int ufem_set_kappa(ufem_op* op, int32_t precision, const void* kappa, void* stream) {
+  if (!op) return fail(UFEM_EINVAL, "ufem_set_kappa: null op");
+  if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_set_kappa: bad precision");
+  DeviceGuard g(op->device);
+  auto& d = op->prec[precision];
+  if (!kappa) {
+    d.has_kappa = false;
+    return UFEM_OK;
+  }
+  size_t bytes = (size_t)op->P.seg[5] * (precision == UFEM_F64 ? 8 : 4);
+  hipError_t e = hipMemcpyAsync(d.kappa, kappa, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(e, "ufem_set_kappa");
+  d.has_kappa = true;
+  return UFEM_OK;
+}
+
+static bool overlap2(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+static bool overlap(const void* a, const void* b, size_t n) { return overlap2(a, n, b, n); }
+
+int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* stream) {
+  if (!op || !u || !v) return fail(UFEM_EINVAL, "ufem_apply: null argument");
+  if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_apply: bad precision");
+  const size_t bytes = (size_t)op->P.n_dofs() * (precision == UFEM_F64 ? 8 : 4);
+  if (overlap(u, v, bytes)) return fail(UFEM_EINVAL, "ufem_apply: u and v overlap");
+  DeviceGuard g(op->device);
+  hipError_t e;
+  if (precision == UFEM_F64)
+    e = ufem::launch_operator<double>(op->args<double>(op->prec[0]), op->P.dim, op->P.p, (const double*)u,
+                                      (double*)v, nullptr, nullptr, false, (hipStream_t)stream);
+  else
+    e = ufem::launch_operator<float>(op->args<float>(op->prec[1]), op->P.dim, op->P.p, (const float*)u, (float*)v,
+                                     nullptr, nullptr, false, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(e, "ufem_apply: launch");
+  return UFEM_OK;
+}
+
+int ufem_apply_adjoint(ufem_op* op, int32_t precision, const void* w, const void* u, void* ATw, void* dkappa,
+                       void* stream) {
+  if (!op || !w || !u || !ATw) return fail(UFEM_EINVAL, "ufem_apply_adjoint: null argument");
+  if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_apply_adjoint: bad precision");
+  const size_t s = precision == UFEM_F64 ? 8 : 4;
+  const size_t bytes = (size_t)op->P.n_dofs() * s;
+  if (overlap(w, ATw, bytes) || overlap(u, ATw, bytes)) return fail(UFEM_EINVAL, "ufem_apply_adjoint: output overlaps input");
+  if (dkappa) {
+    const size_t kb = (size_t)op->P.seg[5] * s;
+    if (overlap2(dkappa, kb, ATw, bytes) || overlap2(dkappa, kb, w, bytes) || overlap2(dkappa, kb, u, bytes))
+      return fail(UFEM_EINVAL, "ufem_apply_adjoint: dkappa overlaps a vector");
+  }
+  DeviceGuard g(op->device);
+  hipError_t e;
+  if (precision == UFEM_F64)
+    e = ufem::launch_operator<double>(op->args<double>(op->prec[0]), op->P.dim, op->P.p, (const double*)u,
+                                      (double*)ATw, (const double*)w, (double*)dkappa, true, (hipStream_t)stream);
+  else
+    e = ufem::launch_operator<float>(op->args<float>(op->prec[1]), op->P.dim, op->P.p, (const float*)u,
+                                     (float*)ATw, (const float*)w, (float*)dkappa, true, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(e, "ufem_apply_adjoint: launch");
+  return UFEM_OK;
+}
+
+int ufem_dot(int32_t precision, int64_t n, const void* x, const void* y, double* out, void* stream) {
+  if (!x || !y || !out || n < 0) return fail(UFEM_EINVAL, "ufem_dot: bad argument");
+  if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_dot: bad precision");
+  hipError_t e = ufem::launch_dot(precision, n, x, y, out, (hipStream_t)stream);
+  return e == hipSuccess ? UFEM_OK : hipfail(e, "ufem_dot");
+}
+
+int ufem_axpby(int32_t precision, int64_t n, double a, const void* x, double b, void* y, void* stream) {
+  if (!x || !y || n < 0) return fail(UFEM_EINVAL, "ufem_axpby: bad argument");
+  if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_axpby: bad precision");
+  hipError_t e = ufem::launch_axpby(precision, n, a, x, b, y, (hipStream_t)stream);
+  return e == hipSuccess ? UFEM_OK : hipfail(e, "ufem_axpby");
+}
+
+int ufem_cast(int32_t pin, int32_t pout, int64_t n, const void* x, void* y, void* stream) {
+  if (!x || !y || n < 0) return fail(UFEM_EINVAL, "ufem_cast: bad argument");
+  if ((pin != UFEM_F64 && pin != UFEM_F32) || (pout != UFEM_F64 && pout != UFEM_F32))
+    return fail(UFEM_EINVAL, "ufem_cast: bad precision");
+  const size_t si = pin == UFEM_F64 ? 8 : 4, so = pout == UFEM_F64 ? 8 : 4;
+  if (n > 0 && overlap2(x, (size_t)n * si, y, (size_t)n * so)) return fail(UFEM_EINVAL, "ufem_cast: x and y overlap");
+  hipError_t e = ufem::launch_cast(pin, pout, n, x, y, (hipStream_t)stream);
+  return e == hipSuccess ? UFEM_OK : hipfail(e, "ufem_cast");
+}
+
+}  // extern "C"

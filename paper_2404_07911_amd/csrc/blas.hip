@@ -1,0 +1,105 @@
+// Solver BLAS-1 kernels and the operator dispatch by dimension.
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace ufem {
+namespace {
+
+// ---------------------------------------------------------------- BLAS-1
+template <typename T>
+__global__ void __launch_bounds__(256) dot_kernel(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
+                                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)x[i] * (double)y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+__global__ void zero1_kernel(double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) axpby_kernel(int64_t n, T a, const T* __restrict__ x, T b, T* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) cast_kernel(int64_t n, const TI* __restrict__ x, TO* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (TO)x[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) zero_kernel(int64_t n, T* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = T(0);
+}
+
+int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_operator(const DevArgs<T>& a, int dim, int degree, const T* u, T* v, const T* w_adj, T* dkappa,
+                           bool adjoint, hipStream_t s) {
+  // adjoint: the operator acts on w (A^T w = A w), u enters dkappa only
+  const T* x = adjoint ? w_adj : u;
+  const T* y = adjoint ? u : nullptr;
+  if (dim == 3) return launch_operator_dim<T, 3>(a, degree, x, y, v, dkappa, adjoint, s);
+  if (dim == 2) return launch_operator_dim<T, 2>(a, degree, x, y, v, dkappa, adjoint, s);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_operator<double>(const DevArgs<double>&, int, int, const double*, double*, const double*,
+                                            double*, bool, hipStream_t);
+template hipError_t launch_operator<float>(const DevArgs<float>&, int, int, const float*, float*, const float*, float*,
+                                           bool, hipStream_t);
+
+hipError_t launch_dot(int prec, int64_t n, const void* x, const void* y, double* out, hipStream_t s) {
+  zero1_kernel<<<1, 64, 0, s>>>(out);
+  if (n > 0) {
+    if (prec == 0)
+      dot_kernel<double><<<grid_for(n), 256, 0, s>>>(n, (const double*)x, (const double*)y, out);
+    else
+      dot_kernel<float><<<grid_for(n), 256, 0, s>>>(n, (const float*)x, (const float*)y, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int prec, int64_t n, double a, const void* x, double b, void* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (prec == 0)
+    axpby_kernel<double><<<grid_for(n), 256, 0, s>>>(n, a, (const double*)x, b, (double*)y);
+  else
+    axpby_kernel<float><<<grid_for(n), 256, 0, s>>>(n, (float)a, (const float*)x, (float)b, (float*)y);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(int pin, int pout, int64_t n, const void* x, void* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int g = grid_for(n);
+  if (pin == 0 && pout == 1) cast_kernel<double, float><<<g, 256, 0, s>>>(n, (const double*)x, (float*)y);
+  else if (pin == 1 && pout == 0) cast_kernel<float, double><<<g, 256, 0, s>>>(n, (const float*)x, (double*)y);
+  else if (pin == 0) cast_kernel<double, double><<<g, 256, 0, s>>>(n, (const double*)x, (double*)y);
+  else cast_kernel<float, float><<<g, 256, 0, s>>>(n, (const float*)x, (float*)y);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int prec, int64_t n, void* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (prec == 0) zero_kernel<double><<<grid_for(n), 256, 0, s>>>(n, (double*)y);
+  else zero_kernel<float><<<grid_for(n), 256, 0, s>>>(n, (float*)y);
+  return hipGetLastError();
+}
+
+}  // namespace ufem

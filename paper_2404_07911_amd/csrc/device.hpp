@@ -1,0 +1,81 @@
+// Device-side data of an operator and the launch interface of the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ufem {
+
+// Slot s = 2 * axis + side of an active cell; side 1 is the upper face (the
+// cell is the lower, "-", side of it), side 0 the lower face.
+// flags word of an active cell: bit s -> ghost penalty on slot s,
+// bit 8 + s -> structured SIPG, bit 16 + s -> cut SIPG.
+constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
+
+// Table layout (per precision), K = p + 1:
+//   S [K*K]   S[q*K+i]  = L_i(g_q), GLL Lagrange basis at the Gauss points
+//   DG[K*K]   DG[q*K+r] = l'_r(g_q), derivative of the Gauss Lagrange basis
+//   W [K]     Gauss weights on [0, 1]
+//   E0[K*K]   E0[j*K+l] = L_l^(j)(0)
+//   E1[K*K]   E1[j*K+l] = L_l^(j)(1)
+//   X [K]     GLL nodes
+//   ID[K]     1 / prod_{j != i} (x_i - x_j)
+//   GW[K]     ghost-penalty weights gamma_j, j = 0..p
+struct TabOff {
+  static __host__ __device__ constexpr int S(int) { return 0; }
+  static __host__ __device__ constexpr int DG(int K) { return K * K; }
+  static __host__ __device__ constexpr int W(int K) { return 2 * K * K; }
+  static __host__ __device__ constexpr int E0(int K) { return 2 * K * K + K; }
+  static __host__ __device__ constexpr int E1(int K) { return 3 * K * K + K; }
+  static __host__ __device__ constexpr int X(int K) { return 4 * K * K + K; }
+  static __host__ __device__ constexpr int ID(int K) { return 4 * K * K + 2 * K; }
+  static __host__ __device__ constexpr int GW(int K) { return 4 * K * K + 3 * K; }
+  static __host__ __device__ constexpr int size(int K) { return 4 * K * K + 4 * K; }
+};
+
+template <typename T>
+struct DevArgs {
+  int32_t n_active, n_inside, n_cut;
+  const int32_t* inside;     // active ranks of inside cells
+  const int32_t* cut_order;  // processing order: cut index per slot
+  const int32_t* cut_rank;   // active rank per cut index
+  const int32_t* nb;         // [n_active * 2D] neighbour rank or -1
+  const int32_t* flags;      // [n_active]
+  const int32_t* slot_face;  // [n_active * 2D] face index or -1
+  const int64_t* face_qoff;  // [n_faces] kappa offset of the SIPG points
+  const int32_t* face_qn;    // [n_faces]
+  const int64_t* vol_off;    // [n_cut + 1]
+  const int64_t* surf_off;   // [n_cut + 1]
+  const T* vol_x;            // SoA: vol_x[a * n_vol + q]
+  const T* vol_w;
+  const T* surf_x;           // SoA
+  const T* surf_w;
+  const T* surf_n;           // SoA
+  const T* fcut_x;           // SoA over dim-1 in-face axes, index (qoff - seg3)
+  const T* fcut_w;
+  int64_t n_vol, n_surf, n_fcut;
+  int64_t seg[6];
+  const T* tab;
+  const T* kappa;            // nullptr: kappa = 1
+  T hs;                      // h^(dim - 2)
+  T tau, gamma;
+  int32_t terms;             // term mask
+};
+
+// Launchers: the per-dimension operator kernels live in op_<prec>_<dim>d.hip,
+// the dispatch and the BLAS-1 in blas.hip.
+template <typename T, int D>
+hipError_t launch_operator_dim(const DevArgs<T>& a, int degree, const T* x, const T* y, T* v, T* dkappa, bool adjoint,
+                               hipStream_t s);
+
+template <typename T>
+hipError_t launch_operator(const DevArgs<T>& a, int dim, int degree, const T* u, T* v, const T* w_adj, T* dkappa,
+                           bool adjoint, hipStream_t s);
+
+hipError_t launch_dot(int prec, int64_t n, const void* x, const void* y, double* out, hipStream_t s);
+hipError_t launch_axpby(int prec, int64_t n, double a, const void* x, double b, void* y, hipStream_t s);
+hipError_t launch_cast(int pin, int pout, int64_t n, const void* x, void* y, hipStream_t s);
+hipError_t launch_zero(int prec, int64_t n, void* y, hipStream_t s);
+
+}  // namespace ufem

@@ -1,0 +1,127 @@
+"""CPU tests of the C ABI: the library loads and exports every declared entry
+point, the host plan equals the oracle's classification, faces and
+quadrature, and invalid arguments are rejected."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import ufem_inputs as ui
+from tests.helpers import SMALL_CASES, make_case, oracle_for, oracle_qp_arrays
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2404_07911_amd import _lib
+
+    return _lib
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "ufem.h")).read()
+    declared = sorted(set(re.findall(r"\b(ufem_[a-z_0-9]+)\s*\(", hdr)))
+    assert len(declared) >= 15
+    L = _lib().lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(_lib().exported_symbols()) == declared
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+def test_plan_matches_oracle(name):
+    from paper_2404_07911_amd import Plan, Problem
+
+    wl, _ = make_case(name)
+    pl = Plan(Problem.from_workload(wl))
+    op = oracle_for(wl)
+    assert np.array_equal(pl.cells(), op.cls)
+    kinds = {"str": 0, "cut": 1, "none": 2}
+    of = np.array([(a, b, c, kinds[k], int(g)) for a, b, c, k, g in op.faces], dtype=np.int32).reshape(-1, 5)
+    assert np.array_equal(pl.faces(), of)
+    L = op.layout()
+    assert list(pl.info["seg"]) == list(L["segments"])
+    assert pl.info["n_dofs"] == op.n_dofs
+    xyz, ref, w, nrm = pl.qp()
+    oref, ow, onrm = oracle_qp_arrays(op)
+    assert np.abs(ref - oref).max() < 1e-13
+    assert np.abs(w - ow).max() < 1e-13 * max(1.0, np.abs(ow).max())
+    assert np.abs(nrm - onrm).max() < 1e-13
+    assert np.abs(xyz - op.qp_physical_points()).max() < 1e-13
+
+
+def test_plan_full_size_ball_counts():
+    """The 64^3 degree-3 ball plan builds on the host in seconds and its
+    counts match the oracle's classification."""
+    from paper_2404_07911_amd import Plan, Problem
+    from oracle.geometry import Balls, Mesh, classify_cells
+
+    wl, _ = ui.ball3d(0)
+    pl = Plan(Problem.from_workload(wl))
+    cls = classify_cells(Mesh(3, 64), Balls(wl.centers, wl.radii))
+    assert np.array_equal(pl.cells(), cls)
+    assert pl.info["n_active"] == int(np.sum(cls != 2))
+    assert pl.info["n_dofs"] == pl.info["n_active"] * 64
+    assert pl.info["n_fallback"] == 0
+
+
+def _problem(**over):
+    from paper_2404_07911_amd import Problem
+
+    base = dict(dim=3, n=8, degree=2, centers=np.zeros((1, 3)), radii=np.array([0.5]))
+    base.update(over)
+    return Problem(**base)
+
+
+@pytest.mark.parametrize(
+    "over",
+    [
+        dict(degree=0),
+        dict(degree=8),
+        dict(dim=4, centers=np.zeros((1, 4))),
+        dict(n=1),
+        dict(radii=np.array([-0.5])),
+        dict(q_cut=99),
+        dict(lo=1.0, hi=-1.0),
+        dict(centers=np.full((1, 3), 5.0)),  # no active cell
+    ],
+)
+def test_plan_rejects_bad_problems(over):
+    from paper_2404_07911_amd import Plan, UfemError
+
+    with pytest.raises(UfemError) as e:
+        Plan(_problem(**over))
+    assert e.value.code in (-1, -4)
+
+
+def test_null_arguments_are_rejected():
+    L = _lib()
+    lib = L.lib()
+    assert lib.ufem_plan_create(None, None) == L.UFEM_EINVAL
+    assert lib.ufem_plan_info(None, None) == L.UFEM_EINVAL
+    assert lib.ufem_apply(None, 0, None, None, None) == L.UFEM_EINVAL
+    assert lib.ufem_apply_adjoint(None, 0, None, None, None, None, None) == L.UFEM_EINVAL
+    assert lib.ufem_set_terms(None, 15) == L.UFEM_EINVAL
+    assert lib.ufem_set_kappa(None, 0, None, None) == L.UFEM_EINVAL
+    assert lib.ufem_dot(0, 10, None, None, None, None) == L.UFEM_EINVAL
+    assert lib.ufem_axpby(0, 10, 1.0, None, 1.0, None, None) == L.UFEM_EINVAL
+    assert lib.ufem_cast(0, 1, 10, None, None, None) == L.UFEM_EINVAL
+    assert lib.ufem_cast(0, 2, 10, C.c_void_p(16), C.c_void_p(4096), None) == L.UFEM_EINVAL
+    assert b"ufem_" in lib.ufem_last_error()
+
+
+def test_setup_without_gpu_fails_cleanly():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2404_07911_amd import Plan, UfemError
+
+    pl = Plan(_problem())
+    L = _lib()
+    h = C.c_void_p()
+    rc = L.lib().ufem_setup(pl.handle, 0, None, 0, C.byref(h))
+    assert rc in (L.UFEM_EHIP, L.UFEM_EINVAL)
+    assert not h.value
