@@ -103,8 +103,9 @@ typedef struct {
  * ball-versus-box distances), the face lists, the dimension-reduction
  * quadrature of every cut cell, cut face and interface piece (Saye 2015, as
  * cited in Sections 1 and 2.3), and the quadrature-point layout.  No GPU is
- * touched.  Errors: EINVAL for out-of-range fields, EUNSUPPORTED when an
- * active cell touches the background boundary. */
+ * touched.  Faces on the boundary of the background box carry no term.
+ * Errors: EINVAL for out-of-range fields or a level set that leaves no active
+ * cell, EUNSUPPORTED beyond 2e9 DoFs, ENOMEM on host allocation failure. */
 int ufem_plan_create(const ufem_problem* prob, ufem_plan** out);
 int ufem_plan_destroy(ufem_plan* plan);
 int ufem_plan_info(const ufem_plan* plan, ufem_info* info);
@@ -146,6 +147,13 @@ int ufem_set_kappa(ufem_op* op, int32_t precision, const void* kappa, void* stre
  * `precision`; u must not overlap v (EINVAL).  Asynchronous on `stream`;
  * allocates nothing. */
 int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* stream);
+
+/* The two kernels of ufem_apply one at a time, for per-kernel timing:
+ * part 1 writes the rows of inside cells (structured cell and face
+ * quadrature), part 2 the rows of cut cells (dimension-reduction quadrature,
+ * interface, cut and structured faces); part 3 is ufem_apply.  Rows of the
+ * other class are left untouched. */
+int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u, void* v, void* stream);
 
 /* Adjoint pass for L(kappa, u) with residual weight w:
  *   ATw := A^T w  (the transposed evaluation, integration and evaluation

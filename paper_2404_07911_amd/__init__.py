@@ -4,13 +4,13 @@ Hot path: v = A u for the SIPG discretisation of the Poisson problem on a
 level-set-cut Cartesian mesh (Bergbauer, Munch, Wall, Kronbichler, arXiv
 2404.07911), with hand-written HIP kernels behind the C ABI in include/ufem.h.
 
-Importing the package loads libufem.so and fails if it has not been built.
+Every entry point loads libufem.so and raises ImportError if it has not been
+built: there is no fallback path.  (`python -m paper_2404_07911_amd.build`
+compiles it.)
 """
 from . import _lib
 from ._lib import F32, F64, TERM_ALL, TERM_GHOST, TERM_NITSCHE, TERM_SIPG, TERM_VOLUME, UfemError
 from .ufem import Operator, Plan, Problem, ufem_apply
-
-_lib.lib()  # fail loudly when the native library is missing
 
 __all__ = [
     "Plan",

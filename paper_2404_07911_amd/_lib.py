@@ -77,6 +77,7 @@ _SIGS = {
     "ufem_set_terms": (C.c_int, [_vp, C.c_int32]),
     "ufem_set_kappa": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
     "ufem_apply": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
+    "ufem_apply_part": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]),
     "ufem_apply_adjoint": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "ufem_dot": (C.c_int, [C.c_int32, C.c_int64, _vp, _vp, _vp, _vp]),
     "ufem_axpby": (C.c_int, [C.c_int32, C.c_int64, C.c_double, _vp, C.c_double, _vp, _vp]),

@@ -207,6 +207,7 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.tau = (T)P.tau;
   a.gamma = (T)P.gamma;
   a.terms = terms;
+  a.parts = 3;
   return a;
 }
 
@@ -447,18 +448,28 @@ static bool overlap2(const void* a, size_t na, const void* b, size_t nb) {
 static bool overlap(const void* a, const void* b, size_t n) { return overlap2(a, n, b, n); }
 
 int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* stream) {
+  return ufem_apply_part(op, precision, 3, u, v, stream);
+}
+
+int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u, void* v, void* stream) {
   if (!op || !u || !v) return fail(UFEM_EINVAL, "ufem_apply: null argument");
+  if (part < 1 || part > 3) return fail(UFEM_EINVAL, "ufem_apply_part: part must be 1, 2 or 3");
   if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_apply: bad precision");
   const size_t bytes = (size_t)op->P.n_dofs() * (precision == UFEM_F64 ? 8 : 4);
   if (overlap(u, v, bytes)) return fail(UFEM_EINVAL, "ufem_apply: u and v overlap");
   DeviceGuard g(op->device);
   hipError_t e;
-  if (precision == UFEM_F64)
-    e = ufem::launch_operator<double>(op->args<double>(op->prec[0]), op->P.dim, op->P.p, (const double*)u,
-                                      (double*)v, nullptr, nullptr, false, (hipStream_t)stream);
-  else
-    e = ufem::launch_operator<float>(op->args<float>(op->prec[1]), op->P.dim, op->P.p, (const float*)u, (float*)v,
-                                     nullptr, nullptr, false, (hipStream_t)stream);
+  if (precision == UFEM_F64) {
+    auto a = op->args<double>(op->prec[0]);
+    a.parts = part;
+    e = ufem::launch_operator<double>(a, op->P.dim, op->P.p, (const double*)u, (double*)v, nullptr, nullptr, false,
+                                      (hipStream_t)stream);
+  } else {
+    auto a = op->args<float>(op->prec[1]);
+    a.parts = part;
+    e = ufem::launch_operator<float>(a, op->P.dim, op->P.p, (const float*)u, (float*)v, nullptr, nullptr, false,
+                                     (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hipfail(e, "ufem_apply: launch");
   return UFEM_OK;
 }

@@ -61,6 +61,7 @@ struct DevArgs {
   T hs;                      // h^(dim - 2)
   T tau, gamma;
   int32_t terms;             // term mask
+  int32_t parts;             // 1: inside-cell kernel, 2: cut-cell kernel
 };
 
 // Launchers: the per-dimension operator kernels live in op_<prec>_<dim>d.hip,

@@ -663,8 +663,8 @@ __global__ void __launch_bounds__((Shape<K, D>::NT)) cut_kernel(DevArgs<T> a, co
 template <int K, int D, typename T>
 hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, bool adj, hipStream_t s) {
   constexpr int NT = Shape<K, D>::NT;
-  const int gi = (int)std::min<int64_t>(a.n_inside, 1 << 20);
-  const int gc = (int)std::min<int64_t>(a.n_cut, 1 << 20);
+  const int gi = (a.parts & 1) ? (int)std::min<int64_t>(a.n_inside, 1 << 20) : 0;
+  const int gc = (a.parts & 2) ? (int)std::min<int64_t>(a.n_cut, 1 << 20) : 0;
   if (adj) {
     if (gi > 0) inside_kernel<K, D, T, true><<<gi, NT, 0, s>>>(a, x, y, v, dk);
     if (gc > 0) cut_kernel<K, D, T, true><<<gc, NT, 0, s>>>(a, x, y, v, dk);

@@ -75,9 +75,12 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            L.lib().ufem_plan_destroy(h)
-            self._h = None
+        try:
+            if h is not None and h.value:
+                L.lib().ufem_plan_destroy(h)
+        except Exception:  # interpreter shutdown
+            pass
+        self._h = None
 
     @property
     def handle(self):
@@ -148,9 +151,12 @@ class Operator:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            L.lib().ufem_destroy(h)
-            self._h = None
+        try:
+            if h is not None and h.value:
+                L.lib().ufem_destroy(h)
+        except Exception:  # interpreter shutdown
+            pass
+        self._h = None
 
     def _check_vec(self, t, n, name):
         torch = _torch()
@@ -190,6 +196,12 @@ class Operator:
             raise TypeError("u and v must share a dtype")
         L.check(L.lib().ufem_apply(self._h, _prec_of(u), C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
                                    _stream_handle(stream)))
+        return v
+
+    def apply_part(self, part, u, v, stream=None):
+        """One kernel of the apply (1: inside cells, 2: cut cells)."""
+        L.check(L.lib().ufem_apply_part(self._h, _prec_of(u), int(part), C.c_void_p(u.data_ptr()),
+                                        C.c_void_p(v.data_ptr()), _stream_handle(stream)))
         return v
 
     def apply_adjoint(self, w, u, atw=None, dkappa=None, want_dkappa=True, stream=None):
