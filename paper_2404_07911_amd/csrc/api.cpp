@@ -91,6 +91,17 @@ std::vector<double> make_tables(const ufem::Plan& P) {
     t[ufem::TabOff::ID(K) + i] = 1.0 / den;
     t[ufem::TabOff::GW(K) + i] = i <= P.p ? P.gp_w[i] : 0.0;
   }
+  // 1D mass and stiffness of the GLL basis, integrated exactly by the K-point
+  // Gauss rule (degree 2p <= 2K - 1)
+  std::vector<double> dl;
+  for (int q = 0; q < K; ++q) {
+    ufem::lagrange_all(xl, gx[q], 1, dl);
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) {
+        t[ufem::TabOff::M(K) + i * K + j] += gw[q] * dl[i] * dl[j];
+        t[ufem::TabOff::KS(K) + i * K + j] += gw[q] * dl[K + i] * dl[K + j];
+      }
+  }
   return t;
 }
 

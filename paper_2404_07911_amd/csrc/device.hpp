@@ -22,6 +22,8 @@ constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
 //   X [K]     GLL nodes
 //   ID[K]     1 / prod_{j != i} (x_i - x_j)
 //   GW[K]     ghost-penalty weights gamma_j, j = 0..p
+//   M [K*K]   1D mass matrix of the GLL Lagrange basis (exact: Gauss rule)
+//   KS[K*K]   1D stiffness matrix of the GLL Lagrange basis
 struct TabOff {
   static __host__ __device__ constexpr int S(int) { return 0; }
   static __host__ __device__ constexpr int DG(int K) { return K * K; }
@@ -31,7 +33,9 @@ struct TabOff {
   static __host__ __device__ constexpr int X(int K) { return 4 * K * K + K; }
   static __host__ __device__ constexpr int ID(int K) { return 4 * K * K + 2 * K; }
   static __host__ __device__ constexpr int GW(int K) { return 4 * K * K + 3 * K; }
-  static __host__ __device__ constexpr int size(int K) { return 4 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int M(int K) { return 4 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int KS(int K) { return 5 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int size(int K) { return 6 * K * K + 4 * K; }
 };
 
 template <typename T>

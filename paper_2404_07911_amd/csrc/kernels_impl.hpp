@@ -83,6 +83,8 @@ __device__ __forceinline__ void eval_point(const T* u, const T* X, const T* dX, 
     T v = 0, gx = 0, gy = 0, gz = 0;
 #pragma unroll
     for (int m = 0; m < K; ++m) {
+      // keep the loads of one z-layer together: only K^2 DoFs live at a time
+      __builtin_amdgcn_sched_barrier(0);
       T c0 = 0, c1 = 0, c2 = 0;
 #pragma unroll
       for (int j = 0; j < K; ++j) {
@@ -660,11 +662,546 @@ __global__ void __launch_bounds__((Shape<K, D>::NT)) cut_kernel(DevArgs<T> a, co
   }
 }
 
+
+// ------------------------------------------------ inside cells, kappa = 1
+// With a constant coefficient, exact Gauss integration and the Cartesian
+// metric, the operator restricted to an inside cell is a sum of Kronecker
+// products of the 1D GLL mass M and stiffness KS (the structured cell
+// evaluation of Section 3.2 with the quadrature folded into the 1D
+// matrices):
+//   v = hs [ M_z (M_y R_x + M_x R_y) + M_x M_y R_z ],
+//   R_a = KS_a u + sum over the two faces normal to a of C_a,
+// where C_a[layer l, face node f] collects the face terms at the
+// Gauss-Lobatto face nodes: SIPG  e_l sigma (gamma [u] - {d_n u}) - g_l [u] / 2
+// and ghost penalty  sum_j gamma_j E^j_l (d^j u_own - d^j u_nb)
+// (e, g, E^j: value, first and j-th derivative of the own basis at the face);
+// the in-face mass M (x) M of the face integrals is applied by the
+// subsequent passes.  One team of TS threads per cell, CPB cells per block.
+template <int K, int D>
+struct KronShape {
+  static constexpr int ND = ipow(K, D);
+  static constexpr int NF = ipow(K, D - 1);
+  static constexpr int TS = ND <= 8 ? 8 : (ND <= 16 ? 16 : (ND <= 32 ? 32 : (ND <= 64 ? 64 : (ND <= 128 ? 128 : 256))));
+  static constexpr int CPB = 256 / TS;
+  static constexpr int NT = 256;
+};
+
+template <int K, int D, typename T>
+struct KronWork {
+  static constexpr int ND = KronShape<K, D>::ND, CPB = KronShape<K, D>::CPB;
+  T tab[TabOff::size(K)];
+  T U[CPB][ND];
+  T R[CPB][D][ND];
+  T T1[CPB][ND];
+  T T2[CPB][ND];
+};
+
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
+  constexpr int ND = KronShape<K, D>::ND, NF = KronShape<K, D>::NF, TS = KronShape<K, D>::TS,
+                CPB = KronShape<K, D>::CPB;
+  __shared__ KronWork<K, D, T> W;
+  for (int i = threadIdx.x; i < TabOff::size(K); i += blockDim.x) W.tab[i] = a.tab[i];
+  const int team = threadIdx.x / TS, lane = threadIdx.x % TS;
+  const T* M = W.tab + TabOff::M(K);
+  const T* KS = W.tab + TabOff::KS(K);
+  const T* GW = W.tab + TabOff::GW(K);
+  const bool ghost = (a.terms & 8) != 0, sipg = (a.terms & 2) != 0, vol = (a.terms & 1) != 0;
+  T* U = W.U[team];
+  T* T1 = W.T1[team];
+  T* T2 = W.T2[team];
+  for (int base = blockIdx.x * CPB; base < a.n_inside; base += gridDim.x * CPB) {
+    const int ci = base + team;
+    const bool valid = ci < a.n_inside;
+    const int r = valid ? a.inside[ci] : 0;
+    if (valid) {
+      const T* src = x + (int64_t)r * ND;
+      for (int l = lane; l < ND; l += TS) U[l] = src[l];
+    }
+    sync();
+    // R_a = KS_a u (all directions in one pass)
+    if (valid) {
+      for (int idx = lane; idx < ND; idx += TS) {
+        const int i = idx % K, j = (idx / K) % K;
+        T rx = 0, ry = 0, rz = 0;
+        if (vol) {
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            rx += KS[i * K + q] * U[idx + (q - i)];
+            ry += KS[j * K + q] * U[idx + (q - j) * K];
+            if constexpr (D == 3) {
+              const int m = idx / (K * K);
+              rz += KS[m * K + q] * U[idx + (q - m) * K * K];
+            }
+          }
+        }
+        W.R[team][0][idx] = rx;
+        W.R[team][1][idx] = ry;
+        if constexpr (D == 3) W.R[team][2][idx] = rz;
+      }
+    }
+    sync();
+    // face terms: one item per (direction, face node); both faces of a
+    // direction are handled by the same thread (no write conflicts)
+    if (valid && (sipg || ghost)) {
+      const int fl = a.flags[r];
+      for (int it = lane; it < D * NF; it += TS) {
+        const int ax = it / NF, f = it % NF;
+        T C[K];
+#pragma unroll
+        for (int l = 0; l < K; ++l) C[l] = 0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int s = 2 * ax + side;
+          const bool fs = sipg && ((fl >> (kFlagStr + s)) & 1);
+          const bool fg = ghost && ((fl >> (kFlagGP + s)) & 1);
+          if (!fs && !fg) continue;
+          const int nbr = a.nb[(int64_t)r * 2 * D + s];
+          const T* un = x + (int64_t)nbr * ND;
+          const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+          const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+          const T sigma = side ? T(1) : T(-1);
+          T uo[K], unb[K];
+#pragma unroll
+          for (int l = 0; l < K; ++l) {
+            const int ci2 = cell_index<K, D>(ax, f, l);
+            uo[l] = U[ci2];
+            unb[l] = un[ci2];
+          }
+          if (fs) {
+            T ov = 0, od = 0, nv = 0, nd = 0;
+#pragma unroll
+            for (int l = 0; l < K; ++l) {
+              ov += Eo[l] * uo[l];
+              od += Eo[K + l] * uo[l];
+              nv += En[l] * unb[l];
+              nd += En[K + l] * unb[l];
+            }
+            const T J = sigma * (ov - nv);
+            const T A = T(0.5) * (od + nd);
+            const T cv = sigma * (a.gamma * J - A);
+            const T cd = T(-0.5) * J;
+#pragma unroll
+            for (int l = 0; l < K; ++l) C[l] += Eo[l] * cv + Eo[K + l] * cd;
+          }
+          if (fg) {
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) {
+              const T gj = GW[jj];
+              T dj = 0;
+#pragma unroll
+              for (int l = 0; l < K; ++l) dj += Eo[jj * K + l] * uo[l] - En[jj * K + l] * unb[l];
+              dj *= gj;
+#pragma unroll
+              for (int l = 0; l < K; ++l) C[l] += Eo[jj * K + l] * dj;
+            }
+          }
+        }
+#pragma unroll
+        for (int l = 0; l < K; ++l) W.R[team][ax][cell_index<K, D>(ax, f, l)] += C[l];
+      }
+    }
+    sync();
+    if constexpr (D == 3) {
+      // T1 = M_y R_x + M_x R_y ; T2 = M_x R_z
+      if (valid) {
+        for (int idx = lane; idx < ND; idx += TS) {
+          const int i = idx % K, j = (idx / K) % K;
+          T t1 = 0, t2 = 0;
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            t1 += M[j * K + q] * W.R[team][0][idx + (q - j) * K] + M[i * K + q] * W.R[team][1][idx + (q - i)];
+            t2 += M[i * K + q] * W.R[team][2][idx + (q - i)];
+          }
+          T1[idx] = t1;
+          T2[idx] = t2;
+        }
+      }
+      sync();
+      // v = hs (M_z T1 + M_y T2)
+      if (valid) {
+        T* out = v + (int64_t)r * ND;
+        for (int idx = lane; idx < ND; idx += TS) {
+          const int j = (idx / K) % K, m = idx / (K * K);
+          T o = 0;
+#pragma unroll
+          for (int q = 0; q < K; ++q) o += M[m * K + q] * T1[idx + (q - m) * K * K] + M[j * K + q] * T2[idx + (q - j) * K];
+          out[idx] = a.hs * o;
+        }
+      }
+    } else {
+      // v = hs (M_y R_x + M_x R_y)
+      if (valid) {
+        T* out = v + (int64_t)r * ND;
+        for (int idx = lane; idx < ND; idx += TS) {
+          const int i = idx % K, j = idx / K;
+          T o = 0;
+#pragma unroll
+          for (int q = 0; q < K; ++q) o += M[j * K + q] * W.R[team][0][idx + (q - j) * K] + M[i * K + q] * W.R[team][1][idx + (q - i)];
+          out[idx] = a.hs * o;
+        }
+      }
+    }
+    sync();
+  }
+}
+
+
+// ------------------------------------------------ cut cells, register path
+// One wave per cut cell (ND <= 64).  The structured faces of the cell (SIPG on
+// faces inside the domain, ghost penalty) use the Kronecker face pipeline of
+// the inside cells; every unstructured point (volume, interface, cut face)
+// is handled by one lane, which evaluates the 1D Lagrange polynomials at the
+// point, the value and gradient by d nested 1D sums (Section 3.2,
+// unstructured quadrature evaluation) and integrates with the transposed
+// sums into a private register accumulator; one block reduction per cell
+// combines the lanes.  Cut-face points are treated as points on the face of
+// the cell and of its neighbour.
+template <int K, int D>
+struct CutShape {
+  static constexpr int ND = ipow(K, D);
+  static constexpr int NF = ipow(K, D - 1);
+  static constexpr int NT = 64;
+  static constexpr int CH = 16;  // values per reduction round
+};
+
+template <int K, int D, typename T>
+struct CutWork {
+  static constexpr int ND = CutShape<K, D>::ND, NT = CutShape<K, D>::NT, CH = CutShape<K, D>::CH;
+  T tab[TabOff::size(K)];
+  T U[ND];
+  T NB[2 * D][ND];
+  T R[D][ND];
+  T T1[ND];
+  T T2[ND];
+  T OUT[ND];
+  T red[NT * CH];
+  T red2[4 * CH];
+};
+
+// acc (per point) += integration of value coefficient f0 and reference
+// gradient coefficient g against the cell basis
+template <int K, int D, typename T>
+__device__ __forceinline__ void integrate_point(T* acc, const T* X, const T* dX, const T* Y, const T* dY, const T* Z,
+                                                const T* dZ, T f0, const T* g) {
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const T c0 = Z[m] * f0 + dZ[m] * g[2];
+      const T c1 = Z[m] * g[1];
+      const T c2 = Z[m] * g[0];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const T aa = Y[j] * c0 + dY[j] * c1;
+        const T bb = Y[j] * c2;
+#pragma unroll
+        for (int i = 0; i < K; ++i) acc[i + K * j + K * K * m] += X[i] * aa + dX[i] * bb;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const T aa = Y[j] * f0 + dY[j] * g[1];
+      const T bb = Y[j] * g[0];
+#pragma unroll
+      for (int i = 0; i < K; ++i) acc[i + K * j] += X[i] * aa + dX[i] * bb;
+    }
+  }
+}
+
+// OUT += sum over the lanes of acc
+template <int K, int D, typename T>
+__device__ __forceinline__ void block_reduce(CutWork<K, D, T>& W, T* acc) {
+  constexpr int ND = CutShape<K, D>::ND, NT = CutShape<K, D>::NT, CH = CutShape<K, D>::CH;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < (ND + CH - 1) / CH; ++c) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) W.red[t * CH + i] = (c * CH + i < ND) ? acc[c * CH + i] : T(0);
+    sync();
+    {
+      const int i = t % CH, g = t / CH;  // NT / CH = 4 lane groups
+      T sum = 0;
+#pragma unroll
+      for (int l = 0; l < NT / 4; ++l) sum += W.red[(g * (NT / 4) + l) * CH + i];
+      W.red2[g * CH + i] = sum;
+    }
+    sync();
+    if (t < CH && c * CH + t < ND) W.OUT[c * CH + t] += W.red2[t] + W.red2[CH + t] + W.red2[2 * CH + t] + W.red2[3 * CH + t];
+    sync();
+  }
+}
+
+
+// SIPG points of a cut face normal to axis AX, from the side `side` of slot s
+template <int K, int D, int AX, typename T>
+__device__ __forceinline__ void cut_face_points(CutWork<K, D, T>& W, const DevArgs<T>& a, T* acc, int s, int fid,
+                                                const T* __restrict__ xr, const T* __restrict__ xn) {
+  constexpr int NT = CutShape<K, D>::NT;
+  const int side = s & 1;
+  const int64_t koff = a.face_qoff[fid];
+  const int64_t base = koff - a.seg[3];
+  const int nq = a.face_qn[fid];
+  const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+  const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+  const T* Xn = W.tab + TabOff::X(K);
+  const T* ID = W.tab + TabOff::ID(K);
+  const T sigma = side ? T(1) : T(-1);
+#pragma unroll 1
+  for (int qi = threadIdx.x; qi < nq; qi += NT) {
+    const int64_t q = base + qi;
+    T B[6][K];
+    int fa = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d == AX) continue;
+      if (d < D) lagrange1d<K>(Xn, ID, a.fcut_x[fa * a.n_fcut + q], B[2 * d], B[2 * d + 1]);
+      else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) { B[2 * d][i] = 0; B[2 * d + 1][i] = 0; }
+      }
+      ++fa;
+    }
+    T vo, vn, go[3] = {0, 0, 0}, gn[3] = {0, 0, 0};
+    // neighbour: end-point data of the other side along AX
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      B[2 * AX][i] = En[i];
+      B[2 * AX + 1][i] = En[K + i];
+    }
+    eval_point<K, D>(xn, B[0], B[1], B[2], B[3], B[4], B[5], vn, gn);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      B[2 * AX][i] = Eo[i];
+      B[2 * AX + 1][i] = Eo[K + i];
+    }
+    eval_point<K, D>(xr, B[0], B[1], B[2], B[3], B[4], B[5], vo, go);
+    const T J = sigma * (vo - vn);
+    const T A = T(0.5) * (go[AX] + gn[AX]);
+    T c = a.hs * a.fcut_w[q];
+    if (a.kappa) c *= a.kappa[koff + qi];
+    T gg[3] = {0, 0, 0};
+    gg[AX] = T(-0.5) * c * J;
+    integrate_point<K, D>(acc, B[0], B[1], B[2], B[3], B[4], B[5], c * sigma * (a.gamma * J - A), gg);
+  }
+}
+
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(64) cut_fast_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
+  constexpr int ND = CutShape<K, D>::ND, NF = CutShape<K, D>::NF, NT = CutShape<K, D>::NT;
+  __shared__ CutWork<K, D, T> W;
+  for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
+  const int t = threadIdx.x;
+  const T* M = W.tab + TabOff::M(K);
+  const T* GW = W.tab + TabOff::GW(K);
+  const T* Xn = W.tab + TabOff::X(K);
+  const T* ID = W.tab + TabOff::ID(K);
+  const bool ghost = (a.terms & 8) != 0, sipg = (a.terms & 2) != 0;
+  for (int slot = blockIdx.x; slot < a.n_cut; slot += gridDim.x) {
+    const int ci = a.cut_order[slot];
+    const int r = a.cut_rank[ci];
+    const int fl = a.flags[r];
+    // own and neighbour DoFs into LDS (all loads in flight together)
+    {
+      const T* src = x + (int64_t)r * ND;
+      for (int l = t; l < ND; l += NT) W.U[l] = src[l];
+#pragma unroll
+      for (int s = 0; s < 2 * D; ++s) {
+        const bool need = (fl >> (kFlagStr + s) | fl >> (kFlagCut + s) | fl >> (kFlagGP + s)) & 1;
+        if (!need) continue;
+        const int nbr = a.nb[(int64_t)r * 2 * D + s];
+        const T* sn = x + (int64_t)nbr * ND;
+        for (int l = t; l < ND; l += NT) W.NB[s][l] = sn[l];
+      }
+      for (int l = t; l < ND; l += NT) {
+        W.OUT[l] = 0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) W.R[ax][l] = 0;
+      }
+    }
+    sync();
+    // structured faces: Kronecker face pipeline
+    const bool any_str = ((fl >> kFlagStr) & 0xff & (sipg ? 0xff : 0)) | ((fl >> kFlagGP) & 0xff & (ghost ? 0xff : 0));
+    if (any_str) {
+      for (int it = t; it < D * NF; it += NT) {
+        const int ax = it / NF, f = it % NF;
+        T C[K];
+#pragma unroll
+        for (int l = 0; l < K; ++l) C[l] = 0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int s = 2 * ax + side;
+          const bool fs = sipg && ((fl >> (kFlagStr + s)) & 1);
+          const bool fg = ghost && ((fl >> (kFlagGP + s)) & 1);
+          if (!fs && !fg) continue;
+          const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+          const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+          const T sigma = side ? T(1) : T(-1);
+          T uo[K], unb[K];
+#pragma unroll
+          for (int l = 0; l < K; ++l) {
+            const int c2 = cell_index<K, D>(ax, f, l);
+            uo[l] = W.U[c2];
+            unb[l] = W.NB[s][c2];
+          }
+          if (fs) {
+            T ov = 0, od = 0, nv = 0, nd = 0;
+#pragma unroll
+            for (int l = 0; l < K; ++l) {
+              ov += Eo[l] * uo[l];
+              od += Eo[K + l] * uo[l];
+              nv += En[l] * unb[l];
+              nd += En[K + l] * unb[l];
+            }
+            const T J = sigma * (ov - nv);
+            const T A = T(0.5) * (od + nd);
+            const T cv = sigma * (a.gamma * J - A);
+            const T cd = T(-0.5) * J;
+#pragma unroll
+            for (int l = 0; l < K; ++l) C[l] += Eo[l] * cv + Eo[K + l] * cd;
+          }
+          if (fg) {
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj) {
+              T dj = 0;
+#pragma unroll
+              for (int l = 0; l < K; ++l) dj += Eo[jj * K + l] * uo[l] - En[jj * K + l] * unb[l];
+              dj *= GW[jj];
+#pragma unroll
+              for (int l = 0; l < K; ++l) C[l] += Eo[jj * K + l] * dj;
+            }
+          }
+        }
+#pragma unroll
+        for (int l = 0; l < K; ++l) W.R[ax][cell_index<K, D>(ax, f, l)] += C[l];
+      }
+      sync();
+      if constexpr (D == 3) {
+        for (int idx = t; idx < ND; idx += NT) {
+          const int i = idx % K, j = (idx / K) % K;
+          T t1 = 0, t2 = 0;
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            t1 += M[j * K + q] * W.R[0][idx + (q - j) * K] + M[i * K + q] * W.R[1][idx + (q - i)];
+            t2 += M[i * K + q] * W.R[2][idx + (q - i)];
+          }
+          W.T1[idx] = t1;
+          W.T2[idx] = t2;
+        }
+        sync();
+        for (int idx = t; idx < ND; idx += NT) {
+          const int j = (idx / K) % K, m = idx / (K * K);
+          T o = 0;
+#pragma unroll
+          for (int q = 0; q < K; ++q) o += M[m * K + q] * W.T1[idx + (q - m) * K * K] + M[j * K + q] * W.T2[idx + (q - j) * K];
+          W.OUT[idx] = a.hs * o;
+        }
+      } else {
+        for (int idx = t; idx < ND; idx += NT) {
+          const int i = idx % K, j = idx / K;
+          T o = 0;
+#pragma unroll
+          for (int q = 0; q < K; ++q) o += M[j * K + q] * W.R[0][idx + (q - j) * K] + M[i * K + q] * W.R[1][idx + (q - i)];
+          W.OUT[idx] = a.hs * o;
+        }
+      }
+      sync();
+    }
+    // unstructured points: private accumulators; the cell's DoFs are read
+    // through the scalar cache (the address is uniform across the wave)
+    const T* __restrict__ xr = x + (int64_t)r * ND;
+    T acc[ND];
+#pragma unroll
+    for (int l = 0; l < ND; ++l) acc[l] = 0;
+    T B[6][K];
+    if (a.terms & 1) {
+      const int64_t q0 = a.vol_off[ci], q1 = a.vol_off[ci + 1];
+#pragma unroll 1
+      for (int64_t q = q0 + t; q < q1; q += NT) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) lagrange1d<K>(Xn, ID, a.vol_x[d * a.n_vol + q], B[2 * d], B[2 * d + 1]);
+        if constexpr (D == 2) {
+#pragma unroll
+          for (int i = 0; i < K; ++i) { B[4][i] = 0; B[5][i] = 0; }
+        }
+        T val, g[3] = {0, 0, 0};
+        eval_point<K, D>(xr, B[0], B[1], B[2], B[3], B[4], B[5], val, g);
+        T c = a.hs * a.vol_w[q];
+        if (a.kappa) c *= a.kappa[a.seg[1] + q];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[d] *= c;
+        integrate_point<K, D>(acc, B[0], B[1], B[2], B[3], B[4], B[5], T(0), g);
+      }
+    }
+    if (a.terms & 4) {
+      const int64_t q0 = a.surf_off[ci], q1 = a.surf_off[ci + 1];
+#pragma unroll 1
+      for (int64_t q = q0 + t; q < q1; q += NT) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) lagrange1d<K>(Xn, ID, a.surf_x[d * a.n_surf + q], B[2 * d], B[2 * d + 1]);
+        if constexpr (D == 2) {
+#pragma unroll
+          for (int i = 0; i < K; ++i) { B[4][i] = 0; B[5][i] = 0; }
+        }
+        T val, g[3] = {0, 0, 0};
+        eval_point<K, D>(xr, B[0], B[1], B[2], B[3], B[4], B[5], val, g);
+        T c = a.hs * a.surf_w[q];
+        if (a.kappa) c *= a.kappa[a.seg[4] + q];
+        T dn = 0, nv[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          nv[d] = a.surf_n[d * a.n_surf + q];
+          dn += nv[d] * g[d];
+        }
+        const T f0 = c * (a.tau * val - dn);
+        T gg[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gg[d] = -c * val * nv[d];
+        integrate_point<K, D>(acc, B[0], B[1], B[2], B[3], B[4], B[5], f0, gg);
+      }
+    }
+    if (sipg) {
+#pragma unroll 1
+      for (int s = 0; s < 2 * D; ++s) {
+        if (!((fl >> (kFlagCut + s)) & 1)) continue;
+        const int fid = a.slot_face[(int64_t)r * 2 * D + s];
+        const T* xn = x + (int64_t)a.nb[(int64_t)r * 2 * D + s] * ND;
+        if ((s >> 1) == 0) cut_face_points<K, D, 0>(W, a, acc, s, fid, xr, xn);
+        else if ((s >> 1) == 1) cut_face_points<K, D, 1>(W, a, acc, s, fid, xr, xn);
+        else if constexpr (D == 3) cut_face_points<K, D, 2>(W, a, acc, s, fid, xr, xn);
+      }
+    }
+    block_reduce<K, D>(W, acc);
+    T* out = v + (int64_t)r * ND;
+    for (int l = t; l < ND; l += NT) out[l] = W.OUT[l];
+    sync();
+  }
+}
+
 template <int K, int D, typename T>
 hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, bool adj, hipStream_t s) {
   constexpr int NT = Shape<K, D>::NT;
   const int gi = (a.parts & 1) ? (int)std::min<int64_t>(a.n_inside, 1 << 20) : 0;
   const int gc = (a.parts & 2) ? (int)std::min<int64_t>(a.n_cut, 1 << 20) : 0;
+  if (!adj) {
+    if (a.kappa == nullptr) {
+      constexpr int CPB = KronShape<K, D>::CPB;
+      const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CPB - 1) / CPB, 1 << 20) : 0;
+      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v);
+    } else {
+      if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
+    }
+    // the Kronecker face pipeline of the register path assumes kappa = 1
+    bool fast_cut = false;
+    if constexpr (ipow(K, D) <= 64) fast_cut = a.kappa == nullptr;
+    if (fast_cut) {
+      if constexpr (ipow(K, D) <= 64)
+        if (gc > 0) cut_fast_kernel<K, D, T><<<gc, CutShape<K, D>::NT, 0, s>>>(a, x, v);
+    } else {
+      if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
+    }
+    return hipGetLastError();
+  }
   if (adj) {
     if (gi > 0) inside_kernel<K, D, T, true><<<gi, NT, 0, s>>>(a, x, y, v, dk);
     if (gc > 0) cut_kernel<K, D, T, true><<<gc, NT, 0, s>>>(a, x, y, v, dk);
