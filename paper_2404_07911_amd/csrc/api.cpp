@@ -118,6 +118,8 @@ struct ufem_op {
   int32_t *inside = nullptr, *cut_order = nullptr, *cut_rank = nullptr, *nb = nullptr, *flags = nullptr,
           *slot_face = nullptr, *face_qn = nullptr;
   int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
+  int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
+          *line_info = nullptr, *cell_desc = nullptr;
   // per-precision data
   struct Prec {
     void *vol_x = nullptr, *vol_w = nullptr, *surf_x = nullptr, *surf_w = nullptr, *surf_n = nullptr,
@@ -199,6 +201,12 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.slot_face = slot_face;
   a.face_qoff = face_qoff;
   a.face_qn = face_qn;
+  a.cell_line_off = cell_line_off;
+  a.face_lbeg = face_lbeg;
+  a.face_lend = face_lend;
+  a.line_first = line_first;
+  a.line_info = line_info;
+  a.cell_desc = cell_desc;
   a.vol_off = vol_off;
   a.surf_off = surf_off;
   a.vol_x = (const T*)d.vol_x;
@@ -382,6 +390,37 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       face_qoff[i] = P.faces[i].qp_off;
       face_qn[i] = P.faces[i].qp_n;
     }
+    // point lines
+    std::vector<int32_t> cloff(P.cell_line_off.begin(), P.cell_line_off.end());
+    std::vector<int32_t> flb(P.faces.size(), 0), fle(P.faces.size(), 0), linfo(P.line_first.size());
+    for (size_t i = 0; i + 1 < P.face_line_off.size(); ++i) {
+      flb[P.fcut_face[i]] = (int32_t)P.face_line_off[i];
+      fle[P.fcut_face[i]] = (int32_t)P.face_line_off[i + 1];
+    }
+    for (size_t l = 0; l < P.line_first.size(); ++l)
+      linfo[l] = P.line_n[l] | (P.line_axis[l] << 16) | (P.line_kind[l] << 20);
+    // per cut cell: [line begin, volume/interface boundary, line end,
+    // (first line, end line, slot) of each cut face or (0, 0, -1)]
+    std::vector<int32_t> desc(P.cut.size() * 24, 0);
+    for (size_t i = 0; i < P.cut.size(); ++i) {
+      int32_t* d = &desc[i * 24];
+      const int32_t lb = (int32_t)P.cell_line_off[i], le = (int32_t)P.cell_line_off[i + 1];
+      int32_t mid = lb;
+      while (mid < le && P.line_kind[mid] == 0) ++mid;
+      d[0] = lb;
+      d[1] = mid;
+      d[2] = le;
+      for (int f = 0; f < 6; ++f) { d[3 + 3 * f] = 0; d[4 + 3 * f] = 0; d[5 + 3 * f] = -1; }
+      int nf = 0;
+      for (int sl = 0; sl < S; ++sl) {
+        int32_t fi = P.slot_face[(size_t)P.cut[i] * S + sl];
+        if (fi < 0 || P.faces[fi].kind != ufem::kFaceCut) continue;
+        d[3 + 3 * nf] = flb[fi];
+        d[4 + 3 * nf] = fle[fi];
+        d[5 + 3 * nf] = sl;
+        ++nf;
+      }
+    }
     // cut cells processed in decreasing order of quadrature work
     std::vector<int32_t> order(P.cut.size());
     std::iota(order.begin(), order.end(), 0);
@@ -400,7 +439,10 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->cut_rank, P.cut)) || (rc = op->upload((void**)&op->nb, nb)) ||
         (rc = op->upload((void**)&op->flags, flags)) || (rc = op->upload((void**)&op->slot_face, slot_face)) ||
         (rc = op->upload((void**)&op->face_qoff, face_qoff)) || (rc = op->upload((void**)&op->face_qn, face_qn)) ||
-        (rc = op->upload((void**)&op->vol_off, P.vol_off)) || (rc = op->upload((void**)&op->surf_off, P.surf_off))) {
+        (rc = op->upload((void**)&op->vol_off, P.vol_off)) || (rc = op->upload((void**)&op->surf_off, P.surf_off)) ||
+        (rc = op->upload((void**)&op->cell_line_off, cloff)) || (rc = op->upload((void**)&op->face_lbeg, flb)) ||
+        (rc = op->upload((void**)&op->face_lend, fle)) || (rc = op->upload((void**)&op->line_first, P.line_first)) ||
+        (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc))) {
       delete op;
       return rc;
     }

@@ -49,6 +49,12 @@ struct DevArgs {
   const int32_t* slot_face;  // [n_active * 2D] face index or -1
   const int64_t* face_qoff;  // [n_faces] kappa offset of the SIPG points
   const int32_t* face_qn;    // [n_faces]
+  const int32_t* cell_line_off;  // [n_cut + 1] point lines of each cut cell
+  const int32_t* face_lbeg;      // [n_faces] first point line of a cut face
+  const int32_t* face_lend;      // [n_faces]
+  const int32_t* line_first;     // first point of a line
+  const int32_t* line_info;      // count | axis << 16 | kind << 20
+  const int32_t* cell_desc;      // [n_cut * 24] line segments of each cut cell
   const int64_t* vol_off;    // [n_cut + 1]
   const int64_t* surf_off;   // [n_cut + 1]
   const T* vol_x;            // SoA: vol_x[a * n_vol + q]

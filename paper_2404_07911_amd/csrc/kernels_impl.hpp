@@ -682,26 +682,84 @@ struct KronShape {
   static constexpr int ND = ipow(K, D);
   static constexpr int NF = ipow(K, D - 1);
   static constexpr int TS = ND <= 8 ? 8 : (ND <= 16 ? 16 : (ND <= 32 ? 32 : (ND <= 64 ? 64 : (ND <= 128 ? 128 : 256))));
-  static constexpr int CPB = 256 / TS;
+  static constexpr int CPB = 256 / TS;     // cells per pass of the block
+  static constexpr int NIT = 8;            // passes per block
+  static constexpr int CBLK = CPB * NIT;   // cells per block
+  static constexpr int NV = (ND + TS - 1) / TS;          // DoFs per lane
+  static constexpr int NI = (D * NF + TS - 1) / TS;      // face items per lane
   static constexpr int NT = 256;
 };
 
 template <int K, int D, typename T>
 struct KronWork {
-  static constexpr int ND = KronShape<K, D>::ND, CPB = KronShape<K, D>::CPB;
+  static constexpr int ND = KronShape<K, D>::ND, CPB = KronShape<K, D>::CPB, CBLK = KronShape<K, D>::CBLK;
   T tab[TabOff::size(K)];
   T U[CPB][ND];
   T R[CPB][D][ND];
   T T1[CPB][ND];
   T T2[CPB][ND];
+  int cr[CBLK];
+  int cfl[CBLK];
+  int cnb[CBLK][2 * D];
 };
+
+// global reads of one cell pass: the lane's DoFs and, for each face item,
+// the neighbour's K values along the face normal on both faces
+template <int K, int D, typename T>
+struct KronRegs {
+  T u[KronShape<K, D>::NV];
+  T nb[KronShape<K, D>::NI][2][K];
+};
+
+template <int K, int D, typename T>
+__device__ __forceinline__ void kron_fetch(KronWork<K, D, T>& W, const DevArgs<T>& a, const T* __restrict__ x,
+                                           int slot, int lane, KronRegs<K, D, T>& g) {
+  constexpr int ND = KronShape<K, D>::ND, NF = KronShape<K, D>::NF, TS = KronShape<K, D>::TS,
+                NV = KronShape<K, D>::NV, NI = KronShape<K, D>::NI;
+  const int r = W.cr[slot];
+  if (r < 0) return;
+  const int fl = W.cfl[slot];
+  const T* src = x + (int64_t)r * ND;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int l = lane + v * TS;
+    if (l < ND) g.u[v] = src[l];
+  }
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int item = lane + it * TS;
+    if (item >= D * NF) continue;
+    const int ax = item / NF, f = item % NF;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int s = 2 * ax + side;
+      if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+      const T* un = x + (int64_t)W.cnb[slot][s] * ND;
+#pragma unroll
+      for (int l = 0; l < K; ++l) g.nb[it][side][l] = un[cell_index<K, D>(ax, f, l)];
+    }
+  }
+}
 
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
   constexpr int ND = KronShape<K, D>::ND, NF = KronShape<K, D>::NF, TS = KronShape<K, D>::TS,
-                CPB = KronShape<K, D>::CPB;
+                CPB = KronShape<K, D>::CPB, NIT = KronShape<K, D>::NIT, CBLK = KronShape<K, D>::CBLK,
+                NV = KronShape<K, D>::NV, NI = KronShape<K, D>::NI;
   __shared__ KronWork<K, D, T> W;
   for (int i = threadIdx.x; i < TabOff::size(K); i += blockDim.x) W.tab[i] = a.tab[i];
+  const int c0 = blockIdx.x * CBLK;
+  // the block's cell indices, flags and neighbours in one round of loads
+  for (int i = threadIdx.x; i < CBLK; i += blockDim.x) {
+    const int ci = c0 + i;
+    const bool ok = ci < a.n_inside;
+    const int r = ok ? a.inside[ci] : -1;
+    W.cr[i] = r;
+    W.cfl[i] = ok ? a.flags[r] : 0;
+#pragma unroll
+    for (int s = 0; s < 2 * D; ++s) W.cnb[i][s] = ok ? a.nb[(int64_t)r * 2 * D + s] : 0;
+  }
+  sync();
   const int team = threadIdx.x / TS, lane = threadIdx.x % TS;
   const T* M = W.tab + TabOff::M(K);
   const T* KS = W.tab + TabOff::KS(K);
@@ -710,14 +768,21 @@ __global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T*
   T* U = W.U[team];
   T* T1 = W.T1[team];
   T* T2 = W.T2[team];
-  for (int base = blockIdx.x * CPB; base < a.n_inside; base += gridDim.x * CPB) {
-    const int ci = base + team;
-    const bool valid = ci < a.n_inside;
-    const int r = valid ? a.inside[ci] : 0;
+  KronRegs<K, D, T> cur, nxt;
+  kron_fetch<K, D>(W, a, x, team, lane, cur);
+  for (int pass = 0; pass < NIT; ++pass) {
+    const int slot = pass * CPB + team;
+    const int r = W.cr[slot];
+    const bool valid = r >= 0;
     if (valid) {
-      const T* src = x + (int64_t)r * ND;
-      for (int l = lane; l < ND; l += TS) U[l] = src[l];
+#pragma unroll
+      for (int vv = 0; vv < NV; ++vv) {
+        const int l = lane + vv * TS;
+        if (l < ND) U[l] = cur.u[vv];
+      }
     }
+    // next pass's global reads are in flight while this one computes
+    if (pass + 1 < NIT) kron_fetch<K, D>(W, a, x, slot + CPB, lane, nxt);
     sync();
     // R_a = KS_a u (all directions in one pass)
     if (valid) {
@@ -742,11 +807,14 @@ __global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T*
     }
     sync();
     // face terms: one item per (direction, face node); both faces of a
-    // direction are handled by the same thread (no write conflicts)
+    // direction are handled by the same lane (no write conflicts)
     if (valid && (sipg || ghost)) {
-      const int fl = a.flags[r];
-      for (int it = lane; it < D * NF; it += TS) {
-        const int ax = it / NF, f = it % NF;
+      const int fl = W.cfl[slot];
+#pragma unroll
+      for (int it = 0; it < NI; ++it) {
+        const int item = lane + it * TS;
+        if (item >= D * NF) continue;
+        const int ax = item / NF, f = item % NF;
         T C[K];
 #pragma unroll
         for (int l = 0; l < K; ++l) C[l] = 0;
@@ -756,18 +824,13 @@ __global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T*
           const bool fs = sipg && ((fl >> (kFlagStr + s)) & 1);
           const bool fg = ghost && ((fl >> (kFlagGP + s)) & 1);
           if (!fs && !fg) continue;
-          const int nbr = a.nb[(int64_t)r * 2 * D + s];
-          const T* un = x + (int64_t)nbr * ND;
           const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
           const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
           const T sigma = side ? T(1) : T(-1);
-          T uo[K], unb[K];
+          T uo[K];
 #pragma unroll
-          for (int l = 0; l < K; ++l) {
-            const int ci2 = cell_index<K, D>(ax, f, l);
-            uo[l] = U[ci2];
-            unb[l] = un[ci2];
-          }
+          for (int l = 0; l < K; ++l) uo[l] = U[cell_index<K, D>(ax, f, l)];
+          const T* unb = cur.nb[it][side];
           if (fs) {
             T ov = 0, od = 0, nv = 0, nd = 0;
 #pragma unroll
@@ -787,11 +850,10 @@ __global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T*
           if (fg) {
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
-              const T gj = GW[jj];
               T dj = 0;
 #pragma unroll
               for (int l = 0; l < K; ++l) dj += Eo[jj * K + l] * uo[l] - En[jj * K + l] * unb[l];
-              dj *= gj;
+              dj *= GW[jj];
 #pragma unroll
               for (int l = 0; l < K; ++l) C[l] += Eo[jj * K + l] * dj;
             }
@@ -842,32 +904,34 @@ __global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T*
         }
       }
     }
+    cur = nxt;
     sync();
   }
 }
 
-
-// ------------------------------------------------ cut cells, register path
-// One wave per cut cell (ND <= 64).  The structured faces of the cell (SIPG on
-// faces inside the domain, ghost penalty) use the Kronecker face pipeline of
-// the inside cells; every unstructured point (volume, interface, cut face)
-// is handled by one lane, which evaluates the 1D Lagrange polynomials at the
-// point, the value and gradient by d nested 1D sums (Section 3.2,
-// unstructured quadrature evaluation) and integrates with the transposed
-// sums into a private register accumulator; one block reduction per cell
-// combines the lanes.  Cut-face points are treated as points on the face of
-// the cell and of its neighbour.
+// ------------------------------------------------ cut cells, point lines
+// One wave per cut cell.  The structured faces of the cell (SIPG on faces
+// inside the domain, ghost penalty) use the Kronecker face pipeline of the
+// inside cells.  The unstructured points (volume, interface, cut faces) come
+// in lines: runs of points that share all coordinates but one (the
+// dimension-reduction rule places q Gauss points on each height line).  One
+// lane per line evaluates the 1D Lagrange polynomials of the fixed
+// coordinates, contracts the cell DoFs over the fixed axes once (columns
+// along the line axis), and then needs only 1D sums per point (Section 3.2,
+// unstructured evaluation with the per-point 1D basis reused along the
+// line).  The transposed sums leave a per-line record (fixed-axis basis and
+// line-axis coefficients), and one lane per DoF adds the records of a round.
 template <int K, int D>
-struct CutShape {
+struct LineShape {
   static constexpr int ND = ipow(K, D);
   static constexpr int NF = ipow(K, D - 1);
   static constexpr int NT = 64;
-  static constexpr int CH = 16;  // values per reduction round
+  static constexpr int RS = D == 3 ? 7 * K + 1 : 4 * K + 1;  // record size
 };
 
 template <int K, int D, typename T>
-struct CutWork {
-  static constexpr int ND = CutShape<K, D>::ND, NT = CutShape<K, D>::NT, CH = CutShape<K, D>::CH;
+struct LineWork {
+  static constexpr int ND = LineShape<K, D>::ND, NT = LineShape<K, D>::NT, RS = LineShape<K, D>::RS;
   T tab[TabOff::size(K)];
   T U[ND];
   T NB[2 * D][ND];
@@ -875,133 +939,231 @@ struct CutWork {
   T T1[ND];
   T T2[ND];
   T OUT[ND];
-  T red[NT * CH];
-  T red2[4 * CH];
+  T REC[NT][RS];
+  int desc[24];
+  int segb[2 * D + 1], sege[2 * D + 1], segs[2 * D + 1];
 };
 
-// acc (per point) += integration of value coefficient f0 and reference
-// gradient coefficient g against the cell basis
-template <int K, int D, typename T>
-__device__ __forceinline__ void integrate_point(T* acc, const T* X, const T* dX, const T* Y, const T* dY, const T* Z,
-                                                const T* dZ, T f0, const T* g) {
-  if constexpr (D == 3) {
+// columns along axis KA of the DoF tensor u contracted with (V1, dV1) over
+// the lower other axis and (V2, dV2) over the upper one:
+//   c0 = V1 V2 u, c1 = dV1 V2 u, c2 = V1 dV2 u
+template <int K, int D, int KA, typename T>
+__device__ __forceinline__ void line_columns(const T* u, const T* V1, const T* dV1, const T* V2, const T* dV2, T* c0,
+                                             T* c1, T* c2) {
+  constexpr int O1 = KA == 0 ? 1 : 0;
+  constexpr int O2 = KA == 2 ? 1 : 2;
+  constexpr int SK = ipow(K, KA), S1 = ipow(K, O1), S2 = D == 3 ? ipow(K, O2) : 0;
 #pragma unroll
-    for (int m = 0; m < K; ++m) {
-      const T c0 = Z[m] * f0 + dZ[m] * g[2];
-      const T c1 = Z[m] * g[1];
-      const T c2 = Z[m] * g[0];
+  for (int lk = 0; lk < K; ++lk) {
+    // one layer of loads at a time keeps the register footprint at K^2
+    __builtin_amdgcn_sched_barrier(0);
+    T a0 = 0, a1 = 0, a2 = 0;
+    if constexpr (D == 3) {
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const T aa = Y[j] * c0 + dY[j] * c1;
-        const T bb = Y[j] * c2;
+      for (int b = 0; b < K; ++b) {
+        T s = 0, t = 0;
 #pragma unroll
-        for (int i = 0; i < K; ++i) acc[i + K * j + K * K * m] += X[i] * aa + dX[i] * bb;
+        for (int aa = 0; aa < K; ++aa) {
+          const T uu = u[lk * SK + aa * S1 + b * S2];
+          s += V1[aa] * uu;
+          t += dV1[aa] * uu;
+        }
+        a0 += V2[b] * s;
+        a1 += V2[b] * t;
+        a2 += dV2[b] * s;
       }
+    } else {
+#pragma unroll
+      for (int aa = 0; aa < K; ++aa) {
+        const T uu = u[lk * SK + aa * S1];
+        a0 += V1[aa] * uu;
+        a1 += dV1[aa] * uu;
+      }
+    }
+    c0[lk] = a0;
+    c1[lk] = a1;
+    c2[lk] = a2;
+  }
+}
+
+// one line of points: evaluate, apply the point flux, integrate along the
+// line; writes the line record
+template <int K, int D, int KA, typename T>
+__device__ __forceinline__ void line_work(LineWork<K, D, T>& W, const DevArgs<T>& a, int lid, int slot, T* rec) {
+  constexpr int O1 = KA == 0 ? 1 : 0;
+  constexpr int O2 = KA == 2 ? 1 : 2;
+  const T* Xn = W.tab + TabOff::X(K);
+  const T* ID = W.tab + TabOff::ID(K);
+  const int info = a.line_info[lid];
+  const int n = info & 0xffff, kind = (info >> 20) & 0xf;
+  const int p0 = a.line_first[lid];
+  T V1[K], dV1[K], V2[K], dV2[K];
+  T V1n[K], dV1n[K], V2n[K], dV2n[K];
+  const T* px;
+  int64_t stride;
+  int64_t kbase;
+  const T* pw;
+  const T* En = nullptr;
+  const T* Eo = nullptr;
+  T sigma = 1;
+  int nax = -1;  // face normal axis
+  if (kind == 2) {
+    const int side = slot & 1;
+    nax = slot >> 1;
+    Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+    En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+    sigma = side ? T(1) : T(-1);
+    px = a.fcut_x;
+    stride = a.n_fcut;
+    pw = a.fcut_w;
+    kbase = a.seg[3];
+  } else if (kind == 1) {
+    px = a.surf_x;
+    stride = a.n_surf;
+    pw = a.surf_w;
+    kbase = a.seg[4];
+  } else {
+    px = a.vol_x;
+    stride = a.n_vol;
+    pw = a.vol_w;
+    kbase = a.seg[1];
+  }
+  // coordinate of the point along cell axis ax (faces store in-face axes)
+  auto coord = [&](int64_t q, int ax) -> T {
+    if (kind == 2) {
+      const int fa = ax < nax ? ax : ax - 1;
+      return px[fa * stride + q];
+    }
+    return px[ax * stride + q];
+  };
+  // fixed-axis basis; the face normal axis takes the end-point data
+  if (kind == 2 && O1 == nax) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) { V1[i] = Eo[i]; dV1[i] = Eo[K + i]; V1n[i] = En[i]; dV1n[i] = En[K + i]; }
+  } else {
+    lagrange1d<K>(Xn, ID, coord(p0, O1), V1, dV1);
+#pragma unroll
+    for (int i = 0; i < K; ++i) { V1n[i] = V1[i]; dV1n[i] = dV1[i]; }
+  }
+  if constexpr (D == 3) {
+    if (kind == 2 && O2 == nax) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) { V2[i] = Eo[i]; dV2[i] = Eo[K + i]; V2n[i] = En[i]; dV2n[i] = En[K + i]; }
+    } else {
+      lagrange1d<K>(Xn, ID, coord(p0, O2), V2, dV2);
+#pragma unroll
+      for (int i = 0; i < K; ++i) { V2n[i] = V2[i]; dV2n[i] = dV2[i]; }
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const T aa = Y[j] * f0 + dY[j] * g[1];
-      const T bb = Y[j] * g[0];
-#pragma unroll
-      for (int i = 0; i < K; ++i) acc[i + K * j] += X[i] * aa + dX[i] * bb;
-    }
+    for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; V2n[i] = 1; dV2n[i] = 0; }
   }
-}
-
-// OUT += sum over the lanes of acc
-template <int K, int D, typename T>
-__device__ __forceinline__ void block_reduce(CutWork<K, D, T>& W, T* acc) {
-  constexpr int ND = CutShape<K, D>::ND, NT = CutShape<K, D>::NT, CH = CutShape<K, D>::CH;
-  const int t = threadIdx.x;
+  T c0[K], c1[K], c2[K];
+  line_columns<K, D, KA>(W.U, V1, dV1, V2, dV2, c0, c1, c2);
+  T n0[K], n1[K], n2[K];
+  if (kind == 2) line_columns<K, D, KA>(W.NB[slot], V1n, dV1n, V2n, dV2n, n0, n1, n2);
+  T D0[K], D1[K], D2[K];
 #pragma unroll
-  for (int c = 0; c < (ND + CH - 1) / CH; ++c) {
+  for (int i = 0; i < K; ++i) { D0[i] = 0; D1[i] = 0; D2[i] = 0; }
+  // the point data of up to PB points is loaded in one round
+  constexpr int PB = 4;
+  for (int pb = 0; pb < n; pb += PB) {
+    T tk[PB], wq[PB], nvk[PB], nv1[PB], nv2[PB];
 #pragma unroll
-    for (int i = 0; i < CH; ++i) W.red[t * CH + i] = (c * CH + i < ND) ? acc[c * CH + i] : T(0);
-    sync();
-    {
-      const int i = t % CH, g = t / CH;  // NT / CH = 4 lane groups
-      T sum = 0;
-#pragma unroll
-      for (int l = 0; l < NT / 4; ++l) sum += W.red[(g * (NT / 4) + l) * CH + i];
-      W.red2[g * CH + i] = sum;
-    }
-    sync();
-    if (t < CH && c * CH + t < ND) W.OUT[c * CH + t] += W.red2[t] + W.red2[CH + t] + W.red2[2 * CH + t] + W.red2[3 * CH + t];
-    sync();
-  }
-}
-
-
-// SIPG points of a cut face normal to axis AX, from the side `side` of slot s
-template <int K, int D, int AX, typename T>
-__device__ __forceinline__ void cut_face_points(CutWork<K, D, T>& W, const DevArgs<T>& a, T* acc, int s, int fid,
-                                                const T* __restrict__ xr, const T* __restrict__ xn) {
-  constexpr int NT = CutShape<K, D>::NT;
-  const int side = s & 1;
-  const int64_t koff = a.face_qoff[fid];
-  const int64_t base = koff - a.seg[3];
-  const int nq = a.face_qn[fid];
-  const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-  const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-  const T* Xn = W.tab + TabOff::X(K);
-  const T* ID = W.tab + TabOff::ID(K);
-  const T sigma = side ? T(1) : T(-1);
-#pragma unroll 1
-  for (int qi = threadIdx.x; qi < nq; qi += NT) {
-    const int64_t q = base + qi;
-    T B[6][K];
-    int fa = 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (d == AX) continue;
-      if (d < D) lagrange1d<K>(Xn, ID, a.fcut_x[fa * a.n_fcut + q], B[2 * d], B[2 * d + 1]);
-      else {
-#pragma unroll
-        for (int i = 0; i < K; ++i) { B[2 * d][i] = 0; B[2 * d + 1][i] = 0; }
+    for (int i = 0; i < PB; ++i) {
+      tk[i] = 0; wq[i] = 0; nvk[i] = 0; nv1[i] = 0; nv2[i] = 0;
+      if (pb + i < n) {
+        const int64_t q = p0 + pb + i;
+        tk[i] = coord(q, KA);
+        wq[i] = a.hs * pw[q];
+        if (a.kappa) wq[i] *= a.kappa[kbase + q];
+        if (kind == 1) {
+          nvk[i] = a.surf_n[KA * stride + q];
+          nv1[i] = a.surf_n[O1 * stride + q];
+          if constexpr (D == 3) nv2[i] = a.surf_n[O2 * stride + q];
+        }
       }
-      ++fa;
     }
-    T vo, vn, go[3] = {0, 0, 0}, gn[3] = {0, 0, 0};
-    // neighbour: end-point data of the other side along AX
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      B[2 * AX][i] = En[i];
-      B[2 * AX + 1][i] = En[K + i];
-    }
-    eval_point<K, D>(xn, B[0], B[1], B[2], B[3], B[4], B[5], vn, gn);
+    for (int i = 0; i < PB; ++i) {
+      if (pb + i >= n) break;
+      T Z[K], dZ[K];
+      lagrange1d<K>(Xn, ID, tk[i], Z, dZ);
+      T val = 0, gk = 0, g1 = 0, g2 = 0;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      B[2 * AX][i] = Eo[i];
-      B[2 * AX + 1][i] = Eo[K + i];
+      for (int ii = 0; ii < K; ++ii) {
+        val += Z[ii] * c0[ii];
+        gk += dZ[ii] * c0[ii];
+        g1 += Z[ii] * c1[ii];
+        g2 += Z[ii] * c2[ii];
+      }
+      const T c = wq[i];
+      T f0, fk, f1, f2;
+      if (kind == 0) {
+        f0 = 0;
+        fk = c * gk;
+        f1 = c * g1;
+        f2 = c * g2;
+      } else if (kind == 1) {
+        const T dn = nvk[i] * gk + nv1[i] * g1 + nv2[i] * g2;
+        f0 = c * (a.tau * val - dn);
+        fk = -c * val * nvk[i];
+        f1 = -c * val * nv1[i];
+        f2 = -c * val * nv2[i];
+      } else {
+        T vn = 0, gn1 = 0, gn2 = 0;
+#pragma unroll
+        for (int ii = 0; ii < K; ++ii) {
+          vn += Z[ii] * n0[ii];
+          gn1 += Z[ii] * n1[ii];
+          gn2 += Z[ii] * n2[ii];
+        }
+        // the normal derivative is the fixed-axis derivative of that axis
+        const T go = nax == O1 ? g1 : g2;
+        const T gn = nax == O1 ? gn1 : gn2;
+        const T J = sigma * (val - vn);
+        const T A = T(0.5) * (go + gn);
+        f0 = c * sigma * (a.gamma * J - A);
+        fk = 0;
+        f1 = nax == O1 ? T(-0.5) * c * J : T(0);
+        f2 = nax == O1 ? T(0) : T(-0.5) * c * J;
+      }
+#pragma unroll
+      for (int ii = 0; ii < K; ++ii) {
+        D0[ii] += Z[ii] * f0 + dZ[ii] * fk;
+        D1[ii] += Z[ii] * f1;
+        D2[ii] += Z[ii] * f2;
+      }
     }
-    eval_point<K, D>(xr, B[0], B[1], B[2], B[3], B[4], B[5], vo, go);
-    const T J = sigma * (vo - vn);
-    const T A = T(0.5) * (go[AX] + gn[AX]);
-    T c = a.hs * a.fcut_w[q];
-    if (a.kappa) c *= a.kappa[koff + qi];
-    T gg[3] = {0, 0, 0};
-    gg[AX] = T(-0.5) * c * J;
-    integrate_point<K, D>(acc, B[0], B[1], B[2], B[3], B[4], B[5], c * sigma * (a.gamma * J - A), gg);
+  }
+  rec[0] = T(KA);
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    rec[1 + i] = V1[i];
+    rec[1 + K + i] = dV1[i];
+    rec[1 + 2 * K + i] = D0[i];
+    rec[1 + 3 * K + i] = D1[i];
+    if constexpr (D == 3) {
+      rec[1 + 4 * K + i] = V2[i];
+      rec[1 + 5 * K + i] = dV2[i];
+      rec[1 + 6 * K + i] = D2[i];
+    }
   }
 }
 
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) cut_fast_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
-  constexpr int ND = CutShape<K, D>::ND, NF = CutShape<K, D>::NF, NT = CutShape<K, D>::NT;
-  __shared__ CutWork<K, D, T> W;
+__global__ void __launch_bounds__(64) cut_line_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
+  constexpr int ND = LineShape<K, D>::ND, NF = LineShape<K, D>::NF, NT = LineShape<K, D>::NT;
+  __shared__ LineWork<K, D, T> W;
   for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   const int t = threadIdx.x;
   const T* M = W.tab + TabOff::M(K);
   const T* GW = W.tab + TabOff::GW(K);
-  const T* Xn = W.tab + TabOff::X(K);
-  const T* ID = W.tab + TabOff::ID(K);
   const bool ghost = (a.terms & 8) != 0, sipg = (a.terms & 2) != 0;
   for (int slot = blockIdx.x; slot < a.n_cut; slot += gridDim.x) {
     const int ci = a.cut_order[slot];
     const int r = a.cut_rank[ci];
     const int fl = a.flags[r];
-    // own and neighbour DoFs into LDS (all loads in flight together)
     {
       const T* src = x + (int64_t)r * ND;
       for (int l = t; l < ND; l += NT) W.U[l] = src[l];
@@ -1017,6 +1179,25 @@ __global__ void __launch_bounds__(64) cut_fast_kernel(DevArgs<T> a, const T* __r
         W.OUT[l] = 0;
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) W.R[ax][l] = 0;
+      }
+      if (t < 24) W.desc[t] = a.cell_desc[(int64_t)ci * 24 + t];
+    }
+    sync();
+    if (t == 0) {
+      // line segments of this cell: own volume / interface lines, then the
+      // lines of each cut face (descriptor built on the host)
+      int lb = W.desc[0], mid = W.desc[1], le = W.desc[2];
+      if (!(a.terms & 1)) lb = mid;
+      if (!(a.terms & 4)) le = mid;
+      W.segb[0] = lb;
+      W.sege[0] = le;
+      W.segs[0] = -1;
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) {
+        const bool on = sipg && W.desc[5 + 3 * f] >= 0;
+        W.segb[1 + f] = on ? W.desc[3 + 3 * f] : 0;
+        W.sege[1 + f] = on ? W.desc[4 + 3 * f] : 0;
+        W.segs[1 + f] = W.desc[5 + 3 * f];
       }
     }
     sync();
@@ -1107,71 +1288,53 @@ __global__ void __launch_bounds__(64) cut_fast_kernel(DevArgs<T> a, const T* __r
       }
       sync();
     }
-    // unstructured points: private accumulators; the cell's DoFs are read
-    // through the scalar cache (the address is uniform across the wave)
-    const T* __restrict__ xr = x + (int64_t)r * ND;
-    T acc[ND];
+    // point lines, in rounds of NT lines
+    int total = 0;
 #pragma unroll
-    for (int l = 0; l < ND; ++l) acc[l] = 0;
-    T B[6][K];
-    if (a.terms & 1) {
-      const int64_t q0 = a.vol_off[ci], q1 = a.vol_off[ci + 1];
-#pragma unroll 1
-      for (int64_t q = q0 + t; q < q1; q += NT) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) lagrange1d<K>(Xn, ID, a.vol_x[d * a.n_vol + q], B[2 * d], B[2 * d + 1]);
-        if constexpr (D == 2) {
-#pragma unroll
-          for (int i = 0; i < K; ++i) { B[4][i] = 0; B[5][i] = 0; }
+    for (int sg = 0; sg < 2 * D + 1; ++sg) total += W.sege[sg] - W.segb[sg];
+    for (int base = 0; base < total; base += NT) {
+      const int g = base + t;
+      T* rec = W.REC[t];
+      if (g < total) {
+        int rem = g, sg = 0;
+        while (rem >= W.sege[sg] - W.segb[sg]) {
+          rem -= W.sege[sg] - W.segb[sg];
+          ++sg;
         }
-        T val, g[3] = {0, 0, 0};
-        eval_point<K, D>(xr, B[0], B[1], B[2], B[3], B[4], B[5], val, g);
-        T c = a.hs * a.vol_w[q];
-        if (a.kappa) c *= a.kappa[a.seg[1] + q];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) g[d] *= c;
-        integrate_point<K, D>(acc, B[0], B[1], B[2], B[3], B[4], B[5], T(0), g);
-      }
-    }
-    if (a.terms & 4) {
-      const int64_t q0 = a.surf_off[ci], q1 = a.surf_off[ci + 1];
-#pragma unroll 1
-      for (int64_t q = q0 + t; q < q1; q += NT) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) lagrange1d<K>(Xn, ID, a.surf_x[d * a.n_surf + q], B[2 * d], B[2 * d + 1]);
-        if constexpr (D == 2) {
-#pragma unroll
-          for (int i = 0; i < K; ++i) { B[4][i] = 0; B[5][i] = 0; }
+        const int lid = W.segb[sg] + rem;
+        const int s = W.segs[sg];
+        int ax = (a.line_info[lid] >> 16) & 0xf;
+        if (s >= 0) {  // in-face axis index -> cell axis
+          const int nax = s >> 1;
+          ax = ax < nax ? ax : ax + 1;
         }
-        T val, g[3] = {0, 0, 0};
-        eval_point<K, D>(xr, B[0], B[1], B[2], B[3], B[4], B[5], val, g);
-        T c = a.hs * a.surf_w[q];
-        if (a.kappa) c *= a.kappa[a.seg[4] + q];
-        T dn = 0, nv[3] = {0, 0, 0};
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          nv[d] = a.surf_n[d * a.n_surf + q];
-          dn += nv[d] * g[d];
+        if (ax == 0) line_work<K, D, 0>(W, a, lid, s, rec);
+        else if (ax == 1 || D == 2) line_work<K, D, 1>(W, a, lid, s, rec);
+        else if constexpr (D == 3) line_work<K, D, 2>(W, a, lid, s, rec);
+      }
+      sync();
+      const int nrec = min(NT, total - base);
+      for (int l = t; l < ND; l += NT) {
+        int c[3] = {l % K, (l / K) % K, D == 3 ? l / (K * K) : 0};
+        T sum = 0;
+        for (int rr = 0; rr < nrec; ++rr) {
+          const T* R2 = W.REC[rr];
+          const int ka = (int)R2[0];
+          const int o1 = ka == 0 ? 1 : 0, o2 = ka == 2 ? 1 : 2;
+          const int lk = c[ka], l1 = c[o1];
+          if constexpr (D == 3) {
+            const int l2 = c[o2];
+            const T v2 = R2[1 + 4 * K + l2];
+            sum += v2 * (R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk]) +
+                   R2[1 + l1] * R2[1 + 5 * K + l2] * R2[1 + 6 * K + lk];
+          } else {
+            sum += R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk];
+          }
         }
-        const T f0 = c * (a.tau * val - dn);
-        T gg[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) gg[d] = -c * val * nv[d];
-        integrate_point<K, D>(acc, B[0], B[1], B[2], B[3], B[4], B[5], f0, gg);
+        W.OUT[l] += sum;
       }
+      sync();
     }
-    if (sipg) {
-#pragma unroll 1
-      for (int s = 0; s < 2 * D; ++s) {
-        if (!((fl >> (kFlagCut + s)) & 1)) continue;
-        const int fid = a.slot_face[(int64_t)r * 2 * D + s];
-        const T* xn = x + (int64_t)a.nb[(int64_t)r * 2 * D + s] * ND;
-        if ((s >> 1) == 0) cut_face_points<K, D, 0>(W, a, acc, s, fid, xr, xn);
-        else if ((s >> 1) == 1) cut_face_points<K, D, 1>(W, a, acc, s, fid, xr, xn);
-        else if constexpr (D == 3) cut_face_points<K, D, 2>(W, a, acc, s, fid, xr, xn);
-      }
-    }
-    block_reduce<K, D>(W, acc);
     T* out = v + (int64_t)r * ND;
     for (int l = t; l < ND; l += NT) out[l] = W.OUT[l];
     sync();
@@ -1185,18 +1348,18 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
   const int gc = (a.parts & 2) ? (int)std::min<int64_t>(a.n_cut, 1 << 20) : 0;
   if (!adj) {
     if (a.kappa == nullptr) {
-      constexpr int CPB = KronShape<K, D>::CPB;
-      const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CPB - 1) / CPB, 1 << 20) : 0;
+      constexpr int CBLK = KronShape<K, D>::CBLK;
+      const int gk = (a.parts & 1) ? (int)((a.n_inside + CBLK - 1) / CBLK) : 0;
       if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v);
     } else {
       if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
     }
     // the Kronecker face pipeline of the register path assumes kappa = 1
     bool fast_cut = false;
-    if constexpr (ipow(K, D) <= 64) fast_cut = a.kappa == nullptr;
+    if constexpr (ipow(K, D) <= 125) fast_cut = a.kappa == nullptr;
     if (fast_cut) {
-      if constexpr (ipow(K, D) <= 64)
-        if (gc > 0) cut_fast_kernel<K, D, T><<<gc, CutShape<K, D>::NT, 0, s>>>(a, x, v);
+      if constexpr (ipow(K, D) <= 125)
+        if (gc > 0) cut_line_kernel<K, D, T><<<gc, LineShape<K, D>::NT, 0, s>>>(a, x, v);
     } else {
       if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
     }

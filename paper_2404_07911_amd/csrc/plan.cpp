@@ -527,6 +527,32 @@ void parallel_for(int64_t n, F&& fn) {
   for (auto& t : th) t.join();
 }
 
+
+// Runs of consecutive points [begin, end) (stride `nc` coordinates) in which
+// every point differs from the first one in the same single coordinate.
+void group_lines(const std::vector<double>& x, int nc, int64_t begin, int64_t end, int kind, int default_axis,
+                 Plan& P) {
+  int64_t i = begin;
+  while (i < end) {
+    int64_t j = i + 1;
+    int axis = -1;
+    while (j < end && j - i < 4096) {
+      int ndiff = 0, dax = -1;
+      for (int a = 0; a < nc; ++a)
+        if (x[j * nc + a] != x[i * nc + a]) { ++ndiff; dax = a; }
+      if (ndiff != 1) break;
+      if (axis < 0) axis = dax;
+      else if (dax != axis) break;
+      ++j;
+    }
+    P.line_first.push_back((int32_t)i);
+    P.line_n.push_back((int32_t)(j - i));
+    P.line_axis.push_back(axis < 0 ? default_axis : axis);
+    P.line_kind.push_back(kind);
+    i = j;
+  }
+}
+
 }  // namespace
 
 std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
@@ -694,6 +720,36 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
       P.fcut_w.push_back(R.vw[j] / hd1);
     }
     P.fcut_off[i + 1] = P.fcut_off[i] + (int64_t)R.vw.size();
+  }
+
+  // -- point lines
+  if (P.vol_w.size() > 0x7fffffffu || P.surf_w.size() > 0x7fffffffu || P.fcut_w.size() > 0x7fffffffu) {
+    *code = UFEM_EUNSUPPORTED;
+    return "too many cut quadrature points for 32-bit point indices";
+  }
+  P.line_first.clear(); P.line_n.clear(); P.line_axis.clear(); P.line_kind.clear();
+  P.cell_line_off.assign(ncut + 1, 0);
+  for (size_t i = 0; i < ncut; ++i) {
+    const size_t l0 = P.line_first.size();
+    group_lines(P.vol_x, dim, P.vol_off[i], P.vol_off[i + 1], 0, dim - 1, P);
+    // interface points: one-point lines along the cell's most frequent axis
+    int cnt[3] = {0, 0, 0};
+    for (size_t l = l0; l < P.line_first.size(); ++l) cnt[P.line_axis[l]] += P.line_n[l];
+    int dom = dim - 1;
+    for (int a = 0; a < dim; ++a)
+      if (cnt[a] > cnt[dom]) dom = a;
+    for (int64_t q = P.surf_off[i]; q < P.surf_off[i + 1]; ++q) {
+      P.line_first.push_back((int32_t)q);
+      P.line_n.push_back(1);
+      P.line_axis.push_back(dom);
+      P.line_kind.push_back(1);
+    }
+    P.cell_line_off[i + 1] = (int64_t)P.line_first.size();
+  }
+  P.face_line_off.assign(cutfaces.size() + 1, P.cell_line_off[ncut]);
+  for (size_t i = 0; i < cutfaces.size(); ++i) {
+    group_lines(P.fcut_x, dim - 1, P.fcut_off[i], P.fcut_off[i + 1], 2, 0, P);
+    P.face_line_off[i + 1] = (int64_t)P.line_first.size();
   }
 
   // -- kappa layout

@@ -49,6 +49,16 @@ struct Plan {
   std::vector<int32_t> fcut_face; // face index of each cut face
   std::vector<double> fcut_x, fcut_w;
 
+  // point lines: runs of consecutive points that share every coordinate but
+  // one (the line axis); cell lines hold the volume lines then the interface
+  // points (one-point lines), face lines the points of each cut face
+  std::vector<int64_t> cell_line_off;  // size n_cut + 1
+  std::vector<int64_t> face_line_off;  // size n_faces_cut + 1
+  // per line: first point (index into the vol/surf/fcut arrays), count,
+  // axis (cell axis; for face lines the in-face axis index), kind 0 volume,
+  // 1 interface, 2 cut face
+  std::vector<int32_t> line_first, line_n, line_axis, line_kind;
+
   // kappa layout
   int64_t seg[6] = {0, 0, 0, 0, 0, 0};
   int64_t n_faces_str = 0, n_faces_cut = 0, n_faces_gp = 0;
