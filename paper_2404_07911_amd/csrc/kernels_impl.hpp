@@ -680,231 +680,248 @@ __global__ void __launch_bounds__((Shape<K, D>::NT)) cut_kernel(DevArgs<T> a, co
 template <int K, int D>
 struct KronShape {
   static constexpr int ND = ipow(K, D);
-  static constexpr int NF = ipow(K, D - 1);
-  static constexpr int TS = ND <= 8 ? 8 : (ND <= 16 ? 16 : (ND <= 32 ? 32 : (ND <= 64 ? 64 : (ND <= 128 ? 128 : 256))));
-  static constexpr int CPB = 256 / TS;     // cells per pass of the block
-  static constexpr int NIT = 8;            // passes per block
-  static constexpr int CBLK = CPB * NIT;   // cells per block
-  static constexpr int NV = (ND + TS - 1) / TS;          // DoFs per lane
-  static constexpr int NI = (D * NF + TS - 1) / TS;      // face items per lane
-  static constexpr int NT = 256;
+  static constexpr int NL = ipow(K, D - 1);           // lines per direction
+  static constexpr int C = 64 / NL;                   // cells per wave
+  static constexpr int NT = 64;
 };
 
 template <int K, int D, typename T>
 struct KronWork {
-  static constexpr int ND = KronShape<K, D>::ND, CPB = KronShape<K, D>::CPB, CBLK = KronShape<K, D>::CBLK;
-  T tab[TabOff::size(K)];
-  T U[CPB][ND];
-  T R[CPB][D][ND];
-  T T1[CPB][ND];
-  T T2[CPB][ND];
-  int cr[CBLK];
-  int cfl[CBLK];
-  int cnb[CBLK][2 * D];
+  static constexpr int ND = KronShape<K, D>::ND, C = KronShape<K, D>::C;
+  T A[C][ND];
+  T B[C][ND];
+  T Cc[C][ND];
+  T U[C][ND];
 };
 
-// global reads of one cell pass: the lane's DoFs and, for each face item,
-// the neighbour's K values along the face normal on both faces
-template <int K, int D, typename T>
-struct KronRegs {
-  T u[KronShape<K, D>::NV];
-  T nb[KronShape<K, D>::NI][2][K];
-};
-
-template <int K, int D, typename T>
-__device__ __forceinline__ void kron_fetch(KronWork<K, D, T>& W, const DevArgs<T>& a, const T* __restrict__ x,
-                                           int slot, int lane, KronRegs<K, D, T>& g) {
-  constexpr int ND = KronShape<K, D>::ND, NF = KronShape<K, D>::NF, TS = KronShape<K, D>::TS,
-                NV = KronShape<K, D>::NV, NI = KronShape<K, D>::NI;
-  const int r = W.cr[slot];
-  if (r < 0) return;
-  const int fl = W.cfl[slot];
-  const T* src = x + (int64_t)r * ND;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int l = lane + v * TS;
-    if (l < ND) g.u[v] = src[l];
+// element stride of the lines along axis ax, and the first element of line l
+template <int K, int D, int AX>
+__device__ __forceinline__ constexpr int line_stride() {
+  return ipow(K, AX);
+}
+template <int K, int D, int AX>
+__device__ __forceinline__ int line_base(int l) {
+  if constexpr (D == 2) return AX == 0 ? K * l : l;
+  else {
+    const int a = l % K, b = l / K;
+    if constexpr (AX == 0) return K * a + K * K * b;
+    else if constexpr (AX == 1) return a + K * K * b;
+    else return a + K * b;
   }
+}
+
+// y = M x along a line (M row-major K x K, uniform across the wave)
+template <int K, typename T>
+__device__ __forceinline__ void line_mat(const T* __restrict__ M, const T* x, T* y) {
 #pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int item = lane + it * TS;
-    if (item >= D * NF) continue;
-    const int ax = item / NF, f = item % NF;
+  for (int r = 0; r < K; ++r) {
+    T s = 0;
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int s = 2 * ax + side;
-      if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
-      const T* un = x + (int64_t)W.cnb[slot][s] * ND;
+    for (int q = 0; q < K; ++q) s += M[r * K + q] * x[q];
+    y[r] = s;
+  }
+}
+
+// SIPG and ghost-penalty face terms of the two faces normal to the line
+// axis, added to the line of R (own line uo, neighbour lines nlo / nhi)
+template <int K, typename T>
+__device__ __forceinline__ void line_faces(const T* __restrict__ tab, const DevArgs<T>& a, int fl, int ax,
+                                           const T* uo, const T* nlo, const T* nhi, T* R) {
+  const bool ghost = (a.terms & 8) != 0, sipg = (a.terms & 2) != 0;
 #pragma unroll
-      for (int l = 0; l < K; ++l) g.nb[it][side][l] = un[cell_index<K, D>(ax, f, l)];
+  for (int side = 0; side < 2; ++side) {
+    const int s = 2 * ax + side;
+    const bool fs = sipg && ((fl >> (kFlagStr + s)) & 1);
+    const bool fg = ghost && ((fl >> (kFlagGP + s)) & 1);
+    if (!fs && !fg) continue;
+    const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+    const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+    const T* un = side ? nhi : nlo;
+    const T sigma = side ? T(1) : T(-1);
+    if (fs) {
+      T ov = 0, od = 0, nv = 0, nd = 0;
+#pragma unroll
+      for (int l = 0; l < K; ++l) {
+        ov += Eo[l] * uo[l];
+        od += Eo[K + l] * uo[l];
+        nv += En[l] * un[l];
+        nd += En[K + l] * un[l];
+      }
+      const T J = sigma * (ov - nv);
+      const T Av = T(0.5) * (od + nd);
+      const T cv = sigma * (a.gamma * J - Av);
+      const T cd = T(-0.5) * J;
+#pragma unroll
+      for (int l = 0; l < K; ++l) R[l] += Eo[l] * cv + Eo[K + l] * cd;
+    }
+    if (fg) {
+      const T* GW = tab + TabOff::GW(K);
+#pragma unroll
+      for (int jj = 0; jj < K; ++jj) {
+        T dj = 0;
+#pragma unroll
+        for (int l = 0; l < K; ++l) dj += Eo[jj * K + l] * uo[l] - En[jj * K + l] * un[l];
+        dj *= GW[jj];
+#pragma unroll
+        for (int l = 0; l < K; ++l) R[l] += Eo[jj * K + l] * dj;
+      }
     }
   }
 }
 
+template <int K, int D, int AX, typename T>
+__device__ __forceinline__ void lds_line_load(const T* arr, int base, T* v) {
+#pragma unroll
+  for (int q = 0; q < K; ++q) v[q] = arr[base + q * line_stride<K, D, AX>()];
+}
+template <int K, int D, int AX, typename T>
+__device__ __forceinline__ void lds_line_store(T* arr, int base, const T* v) {
+#pragma unroll
+  for (int q = 0; q < K; ++q) arr[base + q * line_stride<K, D, AX>()] = v[q];
+}
+template <int K, int D, int AX, typename T>
+__device__ __forceinline__ void glb_line_load(const T* __restrict__ src, int base, T* v) {
+#pragma unroll
+  for (int q = 0; q < K; ++q) v[q] = src[base + q * line_stride<K, D, AX>()];
+}
+
+// One wave handles C inside cells; each lane owns one 1D line of its cell
+// in every pass (x-, y-, z-lines in turn), so a contraction costs K loads,
+// K^2 FMAs and K stores per lane and the 1D matrices are wave-uniform:
+//   v = hs [ M_z (M_y R_x + M_x R_y) + M_y M_x R_z ]
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(256) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
-  constexpr int ND = KronShape<K, D>::ND, NF = KronShape<K, D>::NF, TS = KronShape<K, D>::TS,
-                CPB = KronShape<K, D>::CPB, NIT = KronShape<K, D>::NIT, CBLK = KronShape<K, D>::CBLK,
-                NV = KronShape<K, D>::NV, NI = KronShape<K, D>::NI;
+__global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
+  constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
   __shared__ KronWork<K, D, T> W;
-  for (int i = threadIdx.x; i < TabOff::size(K); i += blockDim.x) W.tab[i] = a.tab[i];
-  const int c0 = blockIdx.x * CBLK;
-  // the block's cell indices, flags and neighbours in one round of loads
-  for (int i = threadIdx.x; i < CBLK; i += blockDim.x) {
-    const int ci = c0 + i;
-    const bool ok = ci < a.n_inside;
-    const int r = ok ? a.inside[ci] : -1;
-    W.cr[i] = r;
-    W.cfl[i] = ok ? a.flags[r] : 0;
-#pragma unroll
-    for (int s = 0; s < 2 * D; ++s) W.cnb[i][s] = ok ? a.nb[(int64_t)r * 2 * D + s] : 0;
-  }
-  sync();
-  const int team = threadIdx.x / TS, lane = threadIdx.x % TS;
-  const T* M = W.tab + TabOff::M(K);
-  const T* KS = W.tab + TabOff::KS(K);
-  const T* GW = W.tab + TabOff::GW(K);
-  const bool ghost = (a.terms & 8) != 0, sipg = (a.terms & 2) != 0, vol = (a.terms & 1) != 0;
-  T* U = W.U[team];
-  T* T1 = W.T1[team];
-  T* T2 = W.T2[team];
-  KronRegs<K, D, T> cur, nxt;
-  kron_fetch<K, D>(W, a, x, team, lane, cur);
-  for (int pass = 0; pass < NIT; ++pass) {
-    const int slot = pass * CPB + team;
-    const int r = W.cr[slot];
-    const bool valid = r >= 0;
+  const T* __restrict__ tab = a.tab;
+  const T* M = tab + TabOff::M(K);
+  const T* KS = tab + TabOff::KS(K);
+  const int lane = threadIdx.x;
+  const int c = lane / NL, l = lane % NL;
+  const bool active = c < C;
+  const bool vol = (a.terms & 1) != 0;
+  for (int c0 = blockIdx.x * C; c0 < a.n_inside; c0 += gridDim.x * C) {
+    const int ci = c0 + c;
+    const bool valid = active && ci < a.n_inside;
+    const int r = valid ? a.inside[ci] : 0;
+    const int fl = valid ? a.flags[r] : 0;
+    // global reads of the cell: own x-line and the neighbours' lines through
+    // this lane's face nodes of the x-, y- and z-faces
+    T ux[K], nb[2 * D][K];
+    const int bx = line_base<K, D, 0>(l), by = line_base<K, D, 1>(l);
+    const int bz = D == 3 ? line_base<K, D, 2>(l) : 0;
     if (valid) {
+      glb_line_load<K, D, 0>(x + (int64_t)r * ND, bx, ux);
 #pragma unroll
-      for (int vv = 0; vv < NV; ++vv) {
-        const int l = lane + vv * TS;
-        if (l < ND) U[l] = cur.u[vv];
+      for (int s = 0; s < 2 * D; ++s) {
+        if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+        const T* un = x + (int64_t)a.nb[(int64_t)r * 2 * D + s] * ND;
+        const int ax = s >> 1;
+        if (ax == 0) glb_line_load<K, D, 0>(un, bx, nb[s]);
+        else if (ax == 1) glb_line_load<K, D, 1>(un, by, nb[s]);
+        else if constexpr (D == 3) glb_line_load<K, D, 2>(un, bz, nb[s]);
       }
     }
-    // next pass's global reads are in flight while this one computes
-    if (pass + 1 < NIT) kron_fetch<K, D>(W, a, x, slot + CPB, lane, nxt);
-    sync();
-    // R_a = KS_a u (all directions in one pass)
+    T* U = W.U[active ? c : 0];
+    T* A = W.A[active ? c : 0];
+    T* B = W.B[active ? c : 0];
+    T* Cc = W.Cc[active ? c : 0];
+    T t0[K], t1[K], t2[K];
+    // pass x1: R_x = KS u + x-faces -> A ; u -> U
     if (valid) {
-      for (int idx = lane; idx < ND; idx += TS) {
-        const int i = idx % K, j = (idx / K) % K;
-        T rx = 0, ry = 0, rz = 0;
-        if (vol) {
+      lds_line_store<K, D, 0>(U, bx, ux);
+      if (vol) line_mat<K>(KS, ux, t0);
+      else {
 #pragma unroll
-          for (int q = 0; q < K; ++q) {
-            rx += KS[i * K + q] * U[idx + (q - i)];
-            ry += KS[j * K + q] * U[idx + (q - j) * K];
-            if constexpr (D == 3) {
-              const int m = idx / (K * K);
-              rz += KS[m * K + q] * U[idx + (q - m) * K * K];
-            }
-          }
-        }
-        W.R[team][0][idx] = rx;
-        W.R[team][1][idx] = ry;
-        if constexpr (D == 3) W.R[team][2][idx] = rz;
+        for (int q = 0; q < K; ++q) t0[q] = 0;
       }
-    }
-    sync();
-    // face terms: one item per (direction, face node); both faces of a
-    // direction are handled by the same lane (no write conflicts)
-    if (valid && (sipg || ghost)) {
-      const int fl = W.cfl[slot];
-#pragma unroll
-      for (int it = 0; it < NI; ++it) {
-        const int item = lane + it * TS;
-        if (item >= D * NF) continue;
-        const int ax = item / NF, f = item % NF;
-        T C[K];
-#pragma unroll
-        for (int l = 0; l < K; ++l) C[l] = 0;
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int s = 2 * ax + side;
-          const bool fs = sipg && ((fl >> (kFlagStr + s)) & 1);
-          const bool fg = ghost && ((fl >> (kFlagGP + s)) & 1);
-          if (!fs && !fg) continue;
-          const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-          const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-          const T sigma = side ? T(1) : T(-1);
-          T uo[K];
-#pragma unroll
-          for (int l = 0; l < K; ++l) uo[l] = U[cell_index<K, D>(ax, f, l)];
-          const T* unb = cur.nb[it][side];
-          if (fs) {
-            T ov = 0, od = 0, nv = 0, nd = 0;
-#pragma unroll
-            for (int l = 0; l < K; ++l) {
-              ov += Eo[l] * uo[l];
-              od += Eo[K + l] * uo[l];
-              nv += En[l] * unb[l];
-              nd += En[K + l] * unb[l];
-            }
-            const T J = sigma * (ov - nv);
-            const T A = T(0.5) * (od + nd);
-            const T cv = sigma * (a.gamma * J - A);
-            const T cd = T(-0.5) * J;
-#pragma unroll
-            for (int l = 0; l < K; ++l) C[l] += Eo[l] * cv + Eo[K + l] * cd;
-          }
-          if (fg) {
-#pragma unroll
-            for (int jj = 0; jj < K; ++jj) {
-              T dj = 0;
-#pragma unroll
-              for (int l = 0; l < K; ++l) dj += Eo[jj * K + l] * uo[l] - En[jj * K + l] * unb[l];
-              dj *= GW[jj];
-#pragma unroll
-              for (int l = 0; l < K; ++l) C[l] += Eo[jj * K + l] * dj;
-            }
-          }
-        }
-#pragma unroll
-        for (int l = 0; l < K; ++l) W.R[team][ax][cell_index<K, D>(ax, f, l)] += C[l];
-      }
+      line_faces<K>(tab, a, fl, 0, ux, nb[0], nb[1], t0);
+      lds_line_store<K, D, 0>(A, bx, t0);
     }
     sync();
     if constexpr (D == 3) {
-      // T1 = M_y R_x + M_x R_y ; T2 = M_x R_z
+      // pass y1: R_y = KS u + y-faces -> Cc ; P = M_y R_x -> B
       if (valid) {
-        for (int idx = lane; idx < ND; idx += TS) {
-          const int i = idx % K, j = (idx / K) % K;
-          T t1 = 0, t2 = 0;
+        lds_line_load<K, D, 1>(U, by, t1);
+        if (vol) line_mat<K>(KS, t1, t0);
+        else {
 #pragma unroll
-          for (int q = 0; q < K; ++q) {
-            t1 += M[j * K + q] * W.R[team][0][idx + (q - j) * K] + M[i * K + q] * W.R[team][1][idx + (q - i)];
-            t2 += M[i * K + q] * W.R[team][2][idx + (q - i)];
-          }
-          T1[idx] = t1;
-          T2[idx] = t2;
+          for (int q = 0; q < K; ++q) t0[q] = 0;
         }
+        line_faces<K>(tab, a, fl, 1, t1, nb[2], nb[3], t0);
+        lds_line_store<K, D, 1>(Cc, by, t0);
+        lds_line_load<K, D, 1>(A, by, t1);
+        line_mat<K>(M, t1, t2);
+        lds_line_store<K, D, 1>(B, by, t2);
       }
       sync();
-      // v = hs (M_z T1 + M_y T2)
+      // pass x2: S = P + M_x R_y -> A
       if (valid) {
-        T* out = v + (int64_t)r * ND;
-        for (int idx = lane; idx < ND; idx += TS) {
-          const int j = (idx / K) % K, m = idx / (K * K);
-          T o = 0;
+        lds_line_load<K, D, 0>(Cc, bx, t1);
+        line_mat<K>(M, t1, t2);
+        lds_line_load<K, D, 0>(B, bx, t1);
 #pragma unroll
-          for (int q = 0; q < K; ++q) o += M[m * K + q] * T1[idx + (q - m) * K * K] + M[j * K + q] * T2[idx + (q - j) * K];
-          out[idx] = a.hs * o;
+        for (int q = 0; q < K; ++q) t2[q] += t1[q];
+        lds_line_store<K, D, 0>(A, bx, t2);
+      }
+      sync();
+      // pass z1: R_z = KS u + z-faces -> Cc ; O = M_z S -> B
+      if (valid) {
+        lds_line_load<K, D, 2>(U, bz, t1);
+        if (vol) line_mat<K>(KS, t1, t0);
+        else {
+#pragma unroll
+          for (int q = 0; q < K; ++q) t0[q] = 0;
         }
+        line_faces<K>(tab, a, fl, 2, t1, nb[4], nb[5], t0);
+        lds_line_store<K, D, 2>(Cc, bz, t0);
+        lds_line_load<K, D, 2>(A, bz, t1);
+        line_mat<K>(M, t1, t2);
+        lds_line_store<K, D, 2>(B, bz, t2);
+      }
+      sync();
+      // pass x3: V = M_x R_z -> A
+      if (valid) {
+        lds_line_load<K, D, 0>(Cc, bx, t1);
+        line_mat<K>(M, t1, t2);
+        lds_line_store<K, D, 0>(A, bx, t2);
+      }
+      sync();
+      // pass y2: v = hs (M_y V + O)
+      if (valid) {
+        lds_line_load<K, D, 1>(A, by, t1);
+        line_mat<K>(M, t1, t2);
+        lds_line_load<K, D, 1>(B, by, t1);
+        T* out = v + (int64_t)r * ND;
+#pragma unroll
+        for (int q = 0; q < K; ++q) out[by + q * K] = a.hs * (t2[q] + t1[q]);
       }
     } else {
-      // v = hs (M_y R_x + M_x R_y)
+      // pass y1: R_y = KS u + y-faces -> Cc ; P = M_y R_x -> B
       if (valid) {
-        T* out = v + (int64_t)r * ND;
-        for (int idx = lane; idx < ND; idx += TS) {
-          const int i = idx % K, j = idx / K;
-          T o = 0;
+        lds_line_load<K, D, 1>(U, by, t1);
+        if (vol) line_mat<K>(KS, t1, t0);
+        else {
 #pragma unroll
-          for (int q = 0; q < K; ++q) o += M[j * K + q] * W.R[team][0][idx + (q - j) * K] + M[i * K + q] * W.R[team][1][idx + (q - i)];
-          out[idx] = a.hs * o;
+          for (int q = 0; q < K; ++q) t0[q] = 0;
         }
+        line_faces<K>(tab, a, fl, 1, t1, nb[2], nb[3], t0);
+        lds_line_store<K, D, 1>(Cc, by, t0);
+        lds_line_load<K, D, 1>(A, by, t1);
+        line_mat<K>(M, t1, t2);
+        lds_line_store<K, D, 1>(B, by, t2);
+      }
+      sync();
+      // pass x2: v = hs (P + M_x R_y)
+      if (valid) {
+        lds_line_load<K, D, 0>(Cc, bx, t1);
+        line_mat<K>(M, t1, t2);
+        lds_line_load<K, D, 0>(B, bx, t1);
+        T* out = v + (int64_t)r * ND;
+#pragma unroll
+        for (int q = 0; q < K; ++q) out[bx + q] = a.hs * (t2[q] + t1[q]);
       }
     }
-    cur = nxt;
     sync();
   }
 }
@@ -1348,8 +1365,8 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
   const int gc = (a.parts & 2) ? (int)std::min<int64_t>(a.n_cut, 1 << 20) : 0;
   if (!adj) {
     if (a.kappa == nullptr) {
-      constexpr int CBLK = KronShape<K, D>::CBLK;
-      const int gk = (a.parts & 1) ? (int)((a.n_inside + CBLK - 1) / CBLK) : 0;
+      constexpr int CW = KronShape<K, D>::C;
+      const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
       if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v);
     } else {
       if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
