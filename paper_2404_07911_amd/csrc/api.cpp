@@ -101,6 +101,7 @@ std::vector<double> make_tables(const ufem::Plan& P) {
         t[ufem::TabOff::M(K) + i * K + j] += gw[q] * dl[i] * dl[j];
         t[ufem::TabOff::KS(K) + i * K + j] += gw[q] * dl[K + i] * dl[K + j];
       }
+    for (int i = 0; i < K; ++i) t[ufem::TabOff::DS(K) + q * K + i] = dl[K + i];
   }
   return t;
 }
@@ -119,7 +120,9 @@ struct ufem_op {
           *slot_face = nullptr, *face_qn = nullptr;
   int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
   int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
-          *line_info = nullptr, *cell_desc = nullptr;
+          *line_info = nullptr, *cell_desc = nullptr, *vbatch = nullptr, *ventry = nullptr, *fbatch = nullptr,
+          *fentry = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
+  int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0;
   // per-precision data
   struct Prec {
     void *vol_x = nullptr, *vol_w = nullptr, *surf_x = nullptr, *surf_w = nullptr, *surf_n = nullptr,
@@ -207,6 +210,16 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.line_first = line_first;
   a.line_info = line_info;
   a.cell_desc = cell_desc;
+  a.vbatch = vbatch;
+  a.ventry = ventry;
+  a.fbatch = fbatch;
+  a.fentry = fentry;
+  a.n_vbatch = n_vbatch;
+  a.n_fbatch = n_fbatch;
+  a.sf_bm = sf_bm;
+  a.sf_bp = sf_bp;
+  a.sf_ax = sf_ax;
+  a.n_sfaces = n_sfaces;
   a.vol_off = vol_off;
   a.surf_off = surf_off;
   a.vol_x = (const T*)d.vol_x;
@@ -434,6 +447,57 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       cost[i] = c;
     }
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+    // line batches for the cut-cell kernels: cells (most work first) packed
+    // into waves of at most 64 lines; a cell with more lines gets a wave of
+    // its own
+    const int me = P.nd() <= 64 ? 16 : 8;
+    auto make_batches = [&](bool face, std::vector<int32_t>& batches, std::vector<int32_t>& entries) {
+      int cur_lines = 0, cur_n = 0, first = 0;
+      auto close = [&]() {
+        if (cur_n > 0) {
+          batches.push_back(first);
+          batches.push_back(cur_n);
+        }
+        first = (int)(entries.size() / 4);
+        cur_lines = 0;
+        cur_n = 0;
+      };
+      for (int32_t ci : order) {
+        std::vector<int32_t> ce;
+        if (!face) {
+          const int32_t lb = (int32_t)P.cell_line_off[ci], le = (int32_t)P.cell_line_off[ci + 1];
+          if (le > lb) ce.insert(ce.end(), {ci, lb, le, -1});
+        } else {
+          for (int sl = 0; sl < S; ++sl) {
+            int32_t fi = P.slot_face[(size_t)P.cut[ci] * S + sl];
+            if (fi < 0 || P.faces[fi].kind != ufem::kFaceCut || fle[fi] <= flb[fi]) continue;
+            ce.insert(ce.end(), {ci, flb[fi], fle[fi], sl});
+          }
+        }
+        if (ce.empty()) continue;
+        int nl = 0, n_e = (int)ce.size() / 4;
+        for (int e = 0; e < n_e; ++e) nl += ce[4 * e + 2] - ce[4 * e + 1];
+        if (cur_n > 0 && (cur_lines + nl > 64 || cur_n + n_e > me)) close();
+        entries.insert(entries.end(), ce.begin(), ce.end());
+        cur_lines += nl;
+        cur_n += n_e;
+        if (cur_lines >= 64) close();
+      }
+      close();
+    };
+    std::vector<int32_t> sbm, sbp, sax;
+    for (const ufem::Face& f : P.faces)
+      if (f.kind == ufem::kFaceStructured) {
+        sbm.push_back(P.rank[f.bm]);
+        sbp.push_back(P.rank[f.bp]);
+        sax.push_back(f.axis);
+      }
+    op->n_sfaces = (int32_t)sbm.size();
+    std::vector<int32_t> vb, ve, fb, fe;
+    make_batches(false, vb, ve);
+    make_batches(true, fb, fe);
+    op->n_vbatch = (int32_t)(vb.size() / 2);
+    op->n_fbatch = (int32_t)(fb.size() / 2);
     int rc;
     if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->cut_order, order)) ||
         (rc = op->upload((void**)&op->cut_rank, P.cut)) || (rc = op->upload((void**)&op->nb, nb)) ||
@@ -442,7 +506,11 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->vol_off, P.vol_off)) || (rc = op->upload((void**)&op->surf_off, P.surf_off)) ||
         (rc = op->upload((void**)&op->cell_line_off, cloff)) || (rc = op->upload((void**)&op->face_lbeg, flb)) ||
         (rc = op->upload((void**)&op->face_lend, fle)) || (rc = op->upload((void**)&op->line_first, P.line_first)) ||
-        (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc))) {
+        (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc)) ||
+        (rc = op->upload((void**)&op->vbatch, vb)) || (rc = op->upload((void**)&op->ventry, ve)) ||
+        (rc = op->upload((void**)&op->fbatch, fb)) || (rc = op->upload((void**)&op->fentry, fe)) ||
+        (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||
+        (rc = op->upload((void**)&op->sf_ax, sax))) {
       delete op;
       return rc;
     }

@@ -24,6 +24,7 @@ constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
 //   GW[K]     ghost-penalty weights gamma_j, j = 0..p
 //   M [K*K]   1D mass matrix of the GLL Lagrange basis (exact: Gauss rule)
 //   KS[K*K]   1D stiffness matrix of the GLL Lagrange basis
+//   DS[K*K]   DS[q*K+i] = L_i'(g_q), GLL basis derivative at the Gauss points
 struct TabOff {
   static __host__ __device__ constexpr int S(int) { return 0; }
   static __host__ __device__ constexpr int DG(int K) { return K * K; }
@@ -35,7 +36,8 @@ struct TabOff {
   static __host__ __device__ constexpr int GW(int K) { return 4 * K * K + 3 * K; }
   static __host__ __device__ constexpr int M(int K) { return 4 * K * K + 4 * K; }
   static __host__ __device__ constexpr int KS(int K) { return 5 * K * K + 4 * K; }
-  static __host__ __device__ constexpr int size(int K) { return 6 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int DS(int K) { return 6 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int size(int K) { return 7 * K * K + 4 * K; }
 };
 
 template <typename T>
@@ -55,6 +57,19 @@ struct DevArgs {
   const int32_t* line_first;     // first point of a line
   const int32_t* line_info;      // count | axis << 16 | kind << 20
   const int32_t* cell_desc;      // [n_cut * 24] line segments of each cut cell
+  // line batches: batch b covers entries [vbatch[2b], +vbatch[2b+1]); an
+  // entry is (cut index, first line, end line, slot) -- slot -1 for the
+  // volume / interface lines of a cell, the face slot for cut-face lines
+  const int32_t* vbatch;
+  const int32_t* ventry;
+  const int32_t* fbatch;
+  const int32_t* fentry;
+  int32_t n_vbatch, n_fbatch;
+  // structured SIPG faces (kappa order): ranks of the lower / upper cell, axis
+  const int32_t* sf_bm;
+  const int32_t* sf_bp;
+  const int32_t* sf_ax;
+  int32_t n_sfaces;
   const int64_t* vol_off;    // [n_cut + 1]
   const int64_t* surf_off;   // [n_cut + 1]
   const T* vol_x;            // SoA: vol_x[a * n_vol + q]

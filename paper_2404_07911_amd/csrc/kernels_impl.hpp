@@ -790,7 +790,8 @@ __device__ __forceinline__ void glb_line_load(const T* __restrict__ src, int bas
 // K^2 FMAs and K stores per lane and the 1D matrices are wave-uniform:
 //   v = hs [ M_z (M_y R_x + M_x R_y) + M_y M_x R_z ]
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
+__global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+                                                         const int32_t* __restrict__ list, int n_list, int with_volume) {
   constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
   __shared__ KronWork<K, D, T> W;
   const T* __restrict__ tab = a.tab;
@@ -799,11 +800,11 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
   const int lane = threadIdx.x;
   const int c = lane / NL, l = lane % NL;
   const bool active = c < C;
-  const bool vol = (a.terms & 1) != 0;
-  for (int c0 = blockIdx.x * C; c0 < a.n_inside; c0 += gridDim.x * C) {
+  const bool vol = with_volume && (a.terms & 1) != 0;
+  for (int c0 = blockIdx.x * C; c0 < n_list; c0 += gridDim.x * C) {
     const int ci = c0 + c;
-    const bool valid = active && ci < a.n_inside;
-    const int r = valid ? a.inside[ci] : 0;
+    const bool valid = active && ci < n_list;
+    const int r = valid ? list[ci] : 0;
     const int fl = valid ? a.flags[r] : 0;
     // global reads of the cell: own x-line and the neighbours' lines through
     // this lane's face nodes of the x-, y- and z-faces
@@ -946,21 +947,6 @@ struct LineShape {
   static constexpr int RS = D == 3 ? 7 * K + 1 : 4 * K + 1;  // record size
 };
 
-template <int K, int D, typename T>
-struct LineWork {
-  static constexpr int ND = LineShape<K, D>::ND, NT = LineShape<K, D>::NT, RS = LineShape<K, D>::RS;
-  T tab[TabOff::size(K)];
-  T U[ND];
-  T NB[2 * D][ND];
-  T R[D][ND];
-  T T1[ND];
-  T T2[ND];
-  T OUT[ND];
-  T REC[NT][RS];
-  int desc[24];
-  int segb[2 * D + 1], sege[2 * D + 1], segs[2 * D + 1];
-};
-
 // columns along axis KA of the DoF tensor u contracted with (V1, dV1) over
 // the lower other axis and (V2, dV2) over the upper one:
 //   c0 = V1 V2 u, c1 = dV1 V2 u, c2 = V1 dV2 u
@@ -1005,14 +991,16 @@ __device__ __forceinline__ void line_columns(const T* u, const T* V1, const T* d
 
 // one line of points: evaluate, apply the point flux, integrate along the
 // line; writes the line record
-template <int K, int D, int KA, typename T>
-__device__ __forceinline__ void line_work(LineWork<K, D, T>& W, const DevArgs<T>& a, int lid, int slot, T* rec) {
+template <int K, int D, int KA, bool FACE, typename T>
+__device__ __forceinline__ void line_work(const T* tab, const DevArgs<T>& a, int lid, int slot, const T* Uo,
+                                          const T* Un, T* rec) {
   constexpr int O1 = KA == 0 ? 1 : 0;
   constexpr int O2 = KA == 2 ? 1 : 2;
-  const T* Xn = W.tab + TabOff::X(K);
-  const T* ID = W.tab + TabOff::ID(K);
+  const T* Xn = tab + TabOff::X(K);
+  const T* ID = tab + TabOff::ID(K);
   const int info = a.line_info[lid];
-  const int n = info & 0xffff, kind = (info >> 20) & 0xf;
+  const int n = info & 0xffff;
+  const int kind = FACE ? 2 : ((info >> 20) & 0xf);
   const int p0 = a.line_first[lid];
   T V1[K], dV1[K], V2[K], dV2[K];
   T V1n[K], dV1n[K], V2n[K], dV2n[K];
@@ -1027,8 +1015,8 @@ __device__ __forceinline__ void line_work(LineWork<K, D, T>& W, const DevArgs<T>
   if (kind == 2) {
     const int side = slot & 1;
     nax = slot >> 1;
-    Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-    En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+    Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+    En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
     sigma = side ? T(1) : T(-1);
     px = a.fcut_x;
     stride = a.n_fcut;
@@ -1076,9 +1064,9 @@ __device__ __forceinline__ void line_work(LineWork<K, D, T>& W, const DevArgs<T>
     for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; V2n[i] = 1; dV2n[i] = 0; }
   }
   T c0[K], c1[K], c2[K];
-  line_columns<K, D, KA>(W.U, V1, dV1, V2, dV2, c0, c1, c2);
+  line_columns<K, D, KA>(Uo, V1, dV1, V2, dV2, c0, c1, c2);
   T n0[K], n1[K], n2[K];
-  if (kind == 2) line_columns<K, D, KA>(W.NB[slot], V1n, dV1n, V2n, dV2n, n0, n1, n2);
+  if constexpr (FACE) line_columns<K, D, KA>(Un, V1n, dV1n, V2n, dV2n, n0, n1, n2);
   T D0[K], D1[K], D2[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) { D0[i] = 0; D1[i] = 0; D2[i] = 0; }
@@ -1127,7 +1115,7 @@ __device__ __forceinline__ void line_work(LineWork<K, D, T>& W, const DevArgs<T>
         fk = -c * val * nvk[i];
         f1 = -c * val * nv1[i];
         f2 = -c * val * nv2[i];
-      } else {
+      } else if constexpr (FACE) {
         T vn = 0, gn1 = 0, gn2 = 0;
 #pragma unroll
         for (int ii = 0; ii < K; ++ii) {
@@ -1144,6 +1132,8 @@ __device__ __forceinline__ void line_work(LineWork<K, D, T>& W, const DevArgs<T>
         fk = 0;
         f1 = nax == O1 ? T(-0.5) * c * J : T(0);
         f2 = nax == O1 ? T(0) : T(-0.5) * c * J;
+      } else {
+        f0 = fk = f1 = f2 = 0;
       }
 #pragma unroll
       for (int ii = 0; ii < K; ++ii) {
@@ -1168,192 +1158,500 @@ __device__ __forceinline__ void line_work(LineWork<K, D, T>& W, const DevArgs<T>
   }
 }
 
-template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) cut_line_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
-  constexpr int ND = LineShape<K, D>::ND, NF = LineShape<K, D>::NF, NT = LineShape<K, D>::NT;
-  __shared__ LineWork<K, D, T> W;
+// Batched line kernels: one wave per batch of cut cells whose lines fit in
+// one round (or one cell with several rounds); FACE selects the lines of
+// the cut faces (each entry one face of one cell, with the neighbour's DoFs)
+// instead of the volume and interface lines.  The result is added to v.
+template <int K, int D>
+struct BatchShape {
+  static constexpr int ND = ipow(K, D);
+  static constexpr int NT = 64;
+  static constexpr int ME = ND <= 64 ? 16 : 8;  // entries per batch
+  static constexpr int RS = LineShape<K, D>::RS;
+};
+
+template <int K, int D, typename T, bool FACE>
+struct BatchWork {
+  static constexpr int ND = BatchShape<K, D>::ND, ME = BatchShape<K, D>::ME, NT = BatchShape<K, D>::NT,
+                       RS = BatchShape<K, D>::RS;
+  T tab[TabOff::size(K)];
+  T U[ME][ND];
+  T NB[FACE ? ME : 1][FACE ? ND : 1];
+  T OUT[ME][ND];
+  T REC[NT][RS];
+  int ent[ME][4];
+  int rowr[ME];
+  int lofs[ME + 1];
+};
+
+template <int K, int D, typename T, bool FACE>
+__global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+                                                       const int32_t* __restrict__ batches,
+                                                       const int32_t* __restrict__ entries, int n_batches) {
+  constexpr int ND = BatchShape<K, D>::ND, NT = BatchShape<K, D>::NT;
+  __shared__ BatchWork<K, D, T, FACE> W;
   for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   const int t = threadIdx.x;
-  const T* M = W.tab + TabOff::M(K);
-  const T* GW = W.tab + TabOff::GW(K);
-  const bool ghost = (a.terms & 8) != 0, sipg = (a.terms & 2) != 0;
-  for (int slot = blockIdx.x; slot < a.n_cut; slot += gridDim.x) {
-    const int ci = a.cut_order[slot];
-    const int r = a.cut_rank[ci];
-    const int fl = a.flags[r];
-    {
-      const T* src = x + (int64_t)r * ND;
-      for (int l = t; l < ND; l += NT) W.U[l] = src[l];
-#pragma unroll
-      for (int s = 0; s < 2 * D; ++s) {
-        const bool need = (fl >> (kFlagStr + s) | fl >> (kFlagCut + s) | fl >> (kFlagGP + s)) & 1;
-        if (!need) continue;
-        const int nbr = a.nb[(int64_t)r * 2 * D + s];
-        const T* sn = x + (int64_t)nbr * ND;
-        for (int l = t; l < ND; l += NT) W.NB[s][l] = sn[l];
-      }
-      for (int l = t; l < ND; l += NT) {
-        W.OUT[l] = 0;
-#pragma unroll
-        for (int ax = 0; ax < D; ++ax) W.R[ax][l] = 0;
-      }
-      if (t < 24) W.desc[t] = a.cell_desc[(int64_t)ci * 24 + t];
-    }
+  const bool do_vol = (a.terms & 1) != 0, do_surf = (a.terms & 4) != 0;
+  for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
+    const int e0 = batches[2 * b], ne = batches[2 * b + 1];
+    if (t < 4 * ne) W.ent[t / 4][t % 4] = entries[4 * (e0 + t / 4) + t % 4];
     sync();
+    if (t < ne) {
+      const int r = a.cut_rank[W.ent[t][0]];
+      W.rowr[t] = r;
+    }
     if (t == 0) {
-      // line segments of this cell: own volume / interface lines, then the
-      // lines of each cut face (descriptor built on the host)
-      int lb = W.desc[0], mid = W.desc[1], le = W.desc[2];
-      if (!(a.terms & 1)) lb = mid;
-      if (!(a.terms & 4)) le = mid;
-      W.segb[0] = lb;
-      W.sege[0] = le;
-      W.segs[0] = -1;
-#pragma unroll
-      for (int f = 0; f < 2 * D; ++f) {
-        const bool on = sipg && W.desc[5 + 3 * f] >= 0;
-        W.segb[1 + f] = on ? W.desc[3 + 3 * f] : 0;
-        W.sege[1 + f] = on ? W.desc[4 + 3 * f] : 0;
-        W.segs[1 + f] = W.desc[5 + 3 * f];
+      int acc = 0;
+      for (int e = 0; e < ne; ++e) {
+        W.lofs[e] = acc;
+        acc += W.ent[e][2] - W.ent[e][1];
       }
+      W.lofs[ne] = acc;
     }
     sync();
-    // structured faces: Kronecker face pipeline
-    const bool any_str = ((fl >> kFlagStr) & 0xff & (sipg ? 0xff : 0)) | ((fl >> kFlagGP) & 0xff & (ghost ? 0xff : 0));
-    if (any_str) {
-      for (int it = t; it < D * NF; it += NT) {
-        const int ax = it / NF, f = it % NF;
-        T C[K];
-#pragma unroll
-        for (int l = 0; l < K; ++l) C[l] = 0;
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int s = 2 * ax + side;
-          const bool fs = sipg && ((fl >> (kFlagStr + s)) & 1);
-          const bool fg = ghost && ((fl >> (kFlagGP + s)) & 1);
-          if (!fs && !fg) continue;
-          const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-          const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-          const T sigma = side ? T(1) : T(-1);
-          T uo[K], unb[K];
-#pragma unroll
-          for (int l = 0; l < K; ++l) {
-            const int c2 = cell_index<K, D>(ax, f, l);
-            uo[l] = W.U[c2];
-            unb[l] = W.NB[s][c2];
-          }
-          if (fs) {
-            T ov = 0, od = 0, nv = 0, nd = 0;
-#pragma unroll
-            for (int l = 0; l < K; ++l) {
-              ov += Eo[l] * uo[l];
-              od += Eo[K + l] * uo[l];
-              nv += En[l] * unb[l];
-              nd += En[K + l] * unb[l];
-            }
-            const T J = sigma * (ov - nv);
-            const T A = T(0.5) * (od + nd);
-            const T cv = sigma * (a.gamma * J - A);
-            const T cd = T(-0.5) * J;
-#pragma unroll
-            for (int l = 0; l < K; ++l) C[l] += Eo[l] * cv + Eo[K + l] * cd;
-          }
-          if (fg) {
-#pragma unroll
-            for (int jj = 0; jj < K; ++jj) {
-              T dj = 0;
-#pragma unroll
-              for (int l = 0; l < K; ++l) dj += Eo[jj * K + l] * uo[l] - En[jj * K + l] * unb[l];
-              dj *= GW[jj];
-#pragma unroll
-              for (int l = 0; l < K; ++l) C[l] += Eo[jj * K + l] * dj;
-            }
-          }
-        }
-#pragma unroll
-        for (int l = 0; l < K; ++l) W.R[ax][cell_index<K, D>(ax, f, l)] += C[l];
+    for (int idx = t; idx < ne * ND; idx += NT) {
+      const int e = idx / ND, l = idx % ND;
+      W.U[e][l] = x[(int64_t)W.rowr[e] * ND + l];
+      if constexpr (FACE) {
+        const int nbr = a.nb[(int64_t)W.rowr[e] * 2 * D + W.ent[e][3]];
+        W.NB[e][l] = x[(int64_t)nbr * ND + l];
       }
-      sync();
-      if constexpr (D == 3) {
-        for (int idx = t; idx < ND; idx += NT) {
-          const int i = idx % K, j = (idx / K) % K;
-          T t1 = 0, t2 = 0;
-#pragma unroll
-          for (int q = 0; q < K; ++q) {
-            t1 += M[j * K + q] * W.R[0][idx + (q - j) * K] + M[i * K + q] * W.R[1][idx + (q - i)];
-            t2 += M[i * K + q] * W.R[2][idx + (q - i)];
-          }
-          W.T1[idx] = t1;
-          W.T2[idx] = t2;
-        }
-        sync();
-        for (int idx = t; idx < ND; idx += NT) {
-          const int j = (idx / K) % K, m = idx / (K * K);
-          T o = 0;
-#pragma unroll
-          for (int q = 0; q < K; ++q) o += M[m * K + q] * W.T1[idx + (q - m) * K * K] + M[j * K + q] * W.T2[idx + (q - j) * K];
-          W.OUT[idx] = a.hs * o;
-        }
-      } else {
-        for (int idx = t; idx < ND; idx += NT) {
-          const int i = idx % K, j = idx / K;
-          T o = 0;
-#pragma unroll
-          for (int q = 0; q < K; ++q) o += M[j * K + q] * W.R[0][idx + (q - j) * K] + M[i * K + q] * W.R[1][idx + (q - i)];
-          W.OUT[idx] = a.hs * o;
-        }
-      }
-      sync();
+      W.OUT[e][l] = 0;
     }
-    // point lines, in rounds of NT lines
-    int total = 0;
-#pragma unroll
-    for (int sg = 0; sg < 2 * D + 1; ++sg) total += W.sege[sg] - W.segb[sg];
+    sync();
+    const int total = W.lofs[ne];
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
       T* rec = W.REC[t];
       if (g < total) {
-        int rem = g, sg = 0;
-        while (rem >= W.sege[sg] - W.segb[sg]) {
-          rem -= W.sege[sg] - W.segb[sg];
-          ++sg;
-        }
-        const int lid = W.segb[sg] + rem;
-        const int s = W.segs[sg];
-        int ax = (a.line_info[lid] >> 16) & 0xf;
-        if (s >= 0) {  // in-face axis index -> cell axis
+        int e = 0;
+        while (g >= W.lofs[e + 1]) ++e;
+        const int lid = W.ent[e][1] + (g - W.lofs[e]);
+        const int info = a.line_info[lid];
+        const int kind = (info >> 20) & 0xf;
+        const bool on = FACE || (kind == 0 ? do_vol : do_surf);
+        int ax = (info >> 16) & 0xf;
+        const int s = FACE ? W.ent[e][3] : -1;
+        if constexpr (FACE) {
           const int nax = s >> 1;
           ax = ax < nax ? ax : ax + 1;
         }
-        if (ax == 0) line_work<K, D, 0>(W, a, lid, s, rec);
-        else if (ax == 1 || D == 2) line_work<K, D, 1>(W, a, lid, s, rec);
-        else if constexpr (D == 3) line_work<K, D, 2>(W, a, lid, s, rec);
+        const T* Un = FACE ? &W.NB[e][0] : nullptr;
+        if (!on) {
+          rec[0] = T(0);
+          for (int i = 1; i < BatchShape<K, D>::RS; ++i) rec[i] = T(0);
+        } else if (ax == 0) line_work<K, D, 0, FACE>(W.tab, a, lid, s, W.U[e], Un, rec);
+        else if (ax == 1 || D == 2) line_work<K, D, 1, FACE>(W.tab, a, lid, s, W.U[e], Un, rec);
+        else if constexpr (D == 3) line_work<K, D, 2, FACE>(W.tab, a, lid, s, W.U[e], Un, rec);
       }
       sync();
-      const int nrec = min(NT, total - base);
-      for (int l = t; l < ND; l += NT) {
-        int c[3] = {l % K, (l / K) % K, D == 3 ? l / (K * K) : 0};
-        T sum = 0;
-        for (int rr = 0; rr < nrec; ++rr) {
-          const T* R2 = W.REC[rr];
-          const int ka = (int)R2[0];
-          const int o1 = ka == 0 ? 1 : 0, o2 = ka == 2 ? 1 : 2;
-          const int lk = c[ka], l1 = c[o1];
-          if constexpr (D == 3) {
-            const int l2 = c[o2];
-            const T v2 = R2[1 + 4 * K + l2];
-            sum += v2 * (R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk]) +
-                   R2[1 + l1] * R2[1 + 5 * K + l2] * R2[1 + 6 * K + lk];
-          } else {
-            sum += R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk];
+      // records of this round, entry by entry
+      for (int e = 0; e < ne; ++e) {
+        const int r0 = max(W.lofs[e], base) - base, r1 = min(W.lofs[e + 1], base + NT) - base;
+        if (r1 <= r0) continue;
+        for (int l = t; l < ND; l += NT) {
+          const int c[3] = {l % K, (l / K) % K, D == 3 ? l / (K * K) : 0};
+          T sum = 0;
+          for (int rr = r0; rr < r1; ++rr) {
+            const T* R2 = W.REC[rr];
+            const int ka = (int)R2[0];
+            const int o1 = ka == 0 ? 1 : 0, o2 = ka == 2 ? 1 : 2;
+            const int lk = c[ka], l1 = c[o1];
+            if constexpr (D == 3) {
+              const int l2 = c[o2];
+              const T v2 = R2[1 + 4 * K + l2];
+              sum += v2 * (R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk]) +
+                     R2[1 + l1] * R2[1 + 5 * K + l2] * R2[1 + 6 * K + lk];
+            } else {
+              sum += R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk];
+            }
           }
+          W.OUT[e][l] += sum;
         }
-        W.OUT[l] += sum;
       }
       sync();
     }
-    T* out = v + (int64_t)r * ND;
-    for (int l = t; l < ND; l += NT) out[l] = W.OUT[l];
+    // entries of one cell are consecutive: add their sum once
+    for (int idx = t; idx < ne * ND; idx += NT) {
+      const int e = idx / ND, l = idx % ND;
+      if (e > 0 && W.rowr[e - 1] == W.rowr[e]) continue;
+      T sum = W.OUT[e][l];
+      for (int e2 = e + 1; e2 < ne && W.rowr[e2] == W.rowr[e]; ++e2) sum += W.OUT[e2][l];
+      T* out = v + (int64_t)W.rowr[e] * ND + l;
+      *out += sum;
+    }
+    sync();
+  }
+}
+
+
+// ------------------------------------------------ dL/dkappa, kappa = 1 path
+// dkappa_q = a_q(w, u): the kappa-weighted integrand at quadrature point q
+// evaluated with both arguments (volume: grad w . grad u; SIPG face:
+// -{d_n w}[u] - [w]{d_n u} + gamma [w][u]; interface: -d_n w u - w d_n u +
+// tau w u), times the point's weight and h^(d-2).
+
+// inside cells: reference gradients of w and u at the k^d Gauss points by
+// sum factorisation (one lane per 1D line, as in the Kronecker kernel)
+template <int K, int D, typename T>
+struct DkWork {
+  static constexpr int ND = KronShape<K, D>::ND, C = KronShape<K, D>::C;
+  T A[2][C][ND];
+  T B[2][C][ND];
+  T E[2][C][ND];
+};
+
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __restrict__ w, const T* __restrict__ u,
+                                                       T* __restrict__ dk) {
+  constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
+  __shared__ DkWork<K, D, T> W;
+  const T* __restrict__ tab = a.tab;
+  const T* S = tab + TabOff::S(K);
+  const T* DS = tab + TabOff::DS(K);
+  const T* Wt = tab + TabOff::W(K);
+  const int lane = threadIdx.x;
+  const int c = lane / NL, l = lane % NL;
+  const bool active = c < C;
+  const int cc = active ? c : 0;
+  for (int c0 = blockIdx.x * C; c0 < a.n_inside; c0 += gridDim.x * C) {
+    const int ci = c0 + c;
+    const bool valid = active && ci < a.n_inside;
+    const int r = valid ? a.inside[ci] : 0;
+    const int bx = line_base<K, D, 0>(l), by = line_base<K, D, 1>(l);
+    const int bz = D == 3 ? line_base<K, D, 2>(l) : 0;
+    T t0[K], t1[K], t2[K];
+    if (valid) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        glb_line_load<K, D, 0>((f ? u : w) + (int64_t)r * ND, bx, t0);
+        line_mat<K>(S, t0, t1);
+        line_mat<K>(DS, t0, t2);
+        lds_line_store<K, D, 0>(W.A[f][cc], bx, t1);
+        lds_line_store<K, D, 0>(W.B[f][cc], bx, t2);
+      }
+    }
+    sync();
+    if constexpr (D == 3) {
+      if (valid) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          lds_line_load<K, D, 1>(W.A[f][cc], by, t0);
+          line_mat<K>(S, t0, t1);
+          line_mat<K>(DS, t0, t2);
+          lds_line_store<K, D, 1>(W.A[f][cc], by, t1);  // S S u
+          lds_line_store<K, D, 1>(W.E[f][cc], by, t2);  // DS_y S_x u
+          lds_line_load<K, D, 1>(W.B[f][cc], by, t0);
+          line_mat<K>(S, t0, t1);
+          lds_line_store<K, D, 1>(W.B[f][cc], by, t1);  // S_y DS_x u
+        }
+      }
+      sync();
+      if (valid) {
+        T g[2][3][K];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          lds_line_load<K, D, 2>(W.A[f][cc], bz, t0);
+          line_mat<K>(DS, t0, g[f][2]);
+          lds_line_load<K, D, 2>(W.E[f][cc], bz, t0);
+          line_mat<K>(S, t0, g[f][1]);
+          lds_line_load<K, D, 2>(W.B[f][cc], bz, t0);
+          line_mat<K>(S, t0, g[f][0]);
+        }
+        const int qx = bz % K, qy = bz / K;
+        T* out = dk + a.seg[0] + (int64_t)ci * ND;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const T wq = a.hs * Wt[qx] * Wt[qy] * Wt[q];
+          out[bz + q * K * K] = wq * (g[0][0][q] * g[1][0][q] + g[0][1][q] * g[1][1][q] + g[0][2][q] * g[1][2][q]);
+        }
+      }
+    } else {
+      if (valid) {
+        T g[2][2][K];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          lds_line_load<K, D, 1>(W.A[f][cc], by, t0);
+          line_mat<K>(DS, t0, g[f][1]);
+          lds_line_load<K, D, 1>(W.B[f][cc], by, t0);
+          line_mat<K>(S, t0, g[f][0]);
+        }
+        const int qx = by;
+        T* out = dk + a.seg[0] + (int64_t)ci * ND;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const T wq = a.hs * Wt[qx] * Wt[q];
+          out[by + q * K] = wq * (g[0][0][q] * g[1][0][q] + g[0][1][q] * g[1][1][q]);
+        }
+      }
+    }
+    sync();
+  }
+}
+
+// structured SIPG faces: traces of w and u at the Gauss-Lobatto face nodes
+// from both cells, interpolated to the face Gauss points
+template <int K, int D>
+struct FaceDkShape {
+  static constexpr int NF = ipow(K, D - 1);
+  static constexpr int C = 64 / NF;
+};
+
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __restrict__ w, const T* __restrict__ u,
+                                                     T* __restrict__ dk) {
+  constexpr int ND = ipow(K, D), NF = FaceDkShape<K, D>::NF, C = FaceDkShape<K, D>::C;
+  __shared__ T F[C][4][NF];
+  const T* __restrict__ tab = a.tab;
+  const T* S = tab + TabOff::S(K);
+  const T* Wt = tab + TabOff::W(K);
+  const T* E0 = tab + TabOff::E0(K);
+  const T* E1 = tab + TabOff::E1(K);
+  const int lane = threadIdx.x;
+  const int c = lane / NF, f = lane % NF;
+  const bool active = c < C;
+  const int cc = active ? c : 0;
+  for (int f0 = blockIdx.x * C; f0 < a.n_sfaces; f0 += gridDim.x * C) {
+    const int fi = f0 + c;
+    const bool valid = active && fi < a.n_sfaces;
+    if (valid) {
+      const int ax = a.sf_ax[fi];
+      const int64_t rm = a.sf_bm[fi], rp = a.sf_bp[fi];
+#pragma unroll
+      for (int fld = 0; fld < 2; ++fld) {
+        const T* src = fld ? u : w;
+        T vm = 0, dm = 0, vp = 0, dp = 0;
+#pragma unroll
+        for (int l = 0; l < K; ++l) {
+          const int ci2 = D == 3 ? cell_index<K, D>(ax, f, l) : cell_index<K, D>(ax, f, l);
+          const T xm = src[rm * ND + ci2], xp = src[rp * ND + ci2];
+          vm += E1[l] * xm;
+          dm += E1[K + l] * xm;
+          vp += E0[l] * xp;
+          dp += E0[K + l] * xp;
+        }
+        F[cc][2 * fld][f] = vm - vp;
+        F[cc][2 * fld + 1][f] = T(0.5) * (dm + dp);
+      }
+    }
+    sync();
+    if (valid) {
+      T g[4];
+      const int q0 = f % K, q1 = f / K;
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) {
+        T s2 = 0;
+        if constexpr (D == 3) {
+#pragma unroll
+          for (int b = 0; b < K; ++b) {
+            T s1 = 0;
+#pragma unroll
+            for (int a2 = 0; a2 < K; ++a2) s1 += S[q0 * K + a2] * F[cc][k2][a2 + K * b];
+            s2 += S[q1 * K + b] * s1;
+          }
+        } else {
+#pragma unroll
+          for (int a2 = 0; a2 < K; ++a2) s2 += S[q0 * K + a2] * F[cc][k2][a2];
+        }
+        g[k2] = s2;
+      }
+      const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
+      dk[a.seg[2] + (int64_t)fi * NF + f] = wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]);
+    }
+    sync();
+  }
+}
+
+// cut cells: the point lines of the volume / interface (FACE = false) or of
+// the cut faces (FACE = true), with both arguments evaluated at every point
+template <int K, int D, int KA, bool FACE, typename T>
+__device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int lid, int slot, const T* Wo, const T* Wn,
+                                        const T* Yo, const T* Yn, T* __restrict__ dk) {
+  constexpr int O1 = KA == 0 ? 1 : 0;
+  constexpr int O2 = KA == 2 ? 1 : 2;
+  const T* Xn = tab + TabOff::X(K);
+  const T* ID = tab + TabOff::ID(K);
+  const int info = a.line_info[lid];
+  const int n = info & 0xffff;
+  const int kind = FACE ? 2 : ((info >> 20) & 0xf);
+  const int p0 = a.line_first[lid];
+  const T* px;
+  int64_t stride, kbase;
+  const T* pw;
+  const T* Eo = nullptr;
+  const T* En = nullptr;
+  int nax = -1;
+  if (FACE) {
+    const int side = slot & 1;
+    if (side == 0) return;  // the lower cell of the face writes its points
+    nax = slot >> 1;
+    Eo = tab + TabOff::E1(K);
+    En = tab + TabOff::E0(K);
+    px = a.fcut_x;
+    stride = a.n_fcut;
+    pw = a.fcut_w;
+    kbase = a.seg[3];
+  } else if (kind == 1) {
+    px = a.surf_x;
+    stride = a.n_surf;
+    pw = a.surf_w;
+    kbase = a.seg[4];
+  } else {
+    px = a.vol_x;
+    stride = a.n_vol;
+    pw = a.vol_w;
+    kbase = a.seg[1];
+  }
+  auto coord = [&](int64_t q, int ax) -> T {
+    if (FACE) {
+      const int fa = ax < nax ? ax : ax - 1;
+      return px[fa * stride + q];
+    }
+    return px[ax * stride + q];
+  };
+  T V1[K], dV1[K], V2[K], dV2[K];
+  T V1n[K], dV1n[K], V2n[K], dV2n[K];
+  if (FACE && O1 == nax) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) { V1[i] = Eo[i]; dV1[i] = Eo[K + i]; V1n[i] = En[i]; dV1n[i] = En[K + i]; }
+  } else {
+    lagrange1d<K>(Xn, ID, coord(p0, O1), V1, dV1);
+#pragma unroll
+    for (int i = 0; i < K; ++i) { V1n[i] = V1[i]; dV1n[i] = dV1[i]; }
+  }
+  if constexpr (D == 3) {
+    if (FACE && O2 == nax) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) { V2[i] = Eo[i]; dV2[i] = Eo[K + i]; V2n[i] = En[i]; dV2n[i] = En[K + i]; }
+    } else {
+      lagrange1d<K>(Xn, ID, coord(p0, O2), V2, dV2);
+#pragma unroll
+      for (int i = 0; i < K; ++i) { V2n[i] = V2[i]; dV2n[i] = dV2[i]; }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; V2n[i] = 1; dV2n[i] = 0; }
+  }
+  // columns: [field][own/neighbour][value, d_o1, d_o2][K]
+  T cw[3][K], cu[3][K];
+  line_columns<K, D, KA>(Wo, V1, dV1, V2, dV2, cw[0], cw[1], cw[2]);
+  line_columns<K, D, KA>(Yo, V1, dV1, V2, dV2, cu[0], cu[1], cu[2]);
+  T nw[3][K], nu[3][K];
+  if constexpr (FACE) {
+    line_columns<K, D, KA>(Wn, V1n, dV1n, V2n, dV2n, nw[0], nw[1], nw[2]);
+    line_columns<K, D, KA>(Yn, V1n, dV1n, V2n, dV2n, nu[0], nu[1], nu[2]);
+  }
+  for (int pi = 0; pi < n; ++pi) {
+    const int64_t q = p0 + pi;
+    T Z[K], dZ[K];
+    lagrange1d<K>(Xn, ID, coord(q, KA), Z, dZ);
+    T ew[4] = {0, 0, 0, 0}, eu[4] = {0, 0, 0, 0};  // value, d_k, d_o1, d_o2
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      ew[0] += Z[i] * cw[0][i];
+      ew[1] += dZ[i] * cw[0][i];
+      ew[2] += Z[i] * cw[1][i];
+      ew[3] += Z[i] * cw[2][i];
+      eu[0] += Z[i] * cu[0][i];
+      eu[1] += dZ[i] * cu[0][i];
+      eu[2] += Z[i] * cu[1][i];
+      eu[3] += Z[i] * cu[2][i];
+    }
+    const T c = a.hs * pw[q];
+    T val;
+    if constexpr (FACE) {
+      T vw = 0, vu = 0, gw1 = 0, gw2 = 0, gu1 = 0, gu2 = 0;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        vw += Z[i] * nw[0][i];
+        gw1 += Z[i] * nw[1][i];
+        gw2 += Z[i] * nw[2][i];
+        vu += Z[i] * nu[0][i];
+        gu1 += Z[i] * nu[1][i];
+        gu2 += Z[i] * nu[2][i];
+      }
+      const T Jw = ew[0] - vw, Ju = eu[0] - vu;
+      const T Aw = T(0.5) * ((nax == O1 ? ew[2] : ew[3]) + (nax == O1 ? gw1 : gw2));
+      const T Au = T(0.5) * ((nax == O1 ? eu[2] : eu[3]) + (nax == O1 ? gu1 : gu2));
+      val = -Aw * Ju - Jw * Au + a.gamma * Jw * Ju;
+    } else if (kind == 1) {
+      const T nk = a.surf_n[KA * stride + q], n1v = a.surf_n[O1 * stride + q];
+      const T n2v = D == 3 ? a.surf_n[O2 * stride + q] : T(0);
+      const T dnw = nk * ew[1] + n1v * ew[2] + n2v * ew[3];
+      const T dnu = nk * eu[1] + n1v * eu[2] + n2v * eu[3];
+      val = -dnw * eu[0] - ew[0] * dnu + a.tau * ew[0] * eu[0];
+    } else {
+      val = ew[1] * eu[1] + ew[2] * eu[2] + ew[3] * eu[3];
+    }
+    dk[kbase + q] = c * val;
+  }
+}
+
+template <int K, int D, typename T, bool FACE>
+struct DkBatchWork {
+  static constexpr int ND = BatchShape<K, D>::ND, ME = BatchShape<K, D>::ME;
+  T tab[TabOff::size(K)];
+  T Wo[ME][ND];
+  T Yo[ME][ND];
+  T Wn[FACE ? ME : 1][FACE ? ND : 1];
+  T Yn[FACE ? ME : 1][FACE ? ND : 1];
+  int ent[ME][4];
+  int rowr[ME];
+  int lofs[ME + 1];
+};
+
+template <int K, int D, typename T, bool FACE>
+__global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __restrict__ w, const T* __restrict__ u,
+                                                    T* __restrict__ dk, const int32_t* __restrict__ batches,
+                                                    const int32_t* __restrict__ entries, int n_batches) {
+  constexpr int ND = BatchShape<K, D>::ND, NT = 64;
+  __shared__ DkBatchWork<K, D, T, FACE> W;
+  for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
+  const int t = threadIdx.x;
+  for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
+    const int e0 = batches[2 * b], ne = batches[2 * b + 1];
+    if (t < 4 * ne) W.ent[t / 4][t % 4] = entries[4 * (e0 + t / 4) + t % 4];
+    sync();
+    if (t < ne) W.rowr[t] = a.cut_rank[W.ent[t][0]];
+    if (t == 0) {
+      int acc = 0;
+      for (int e = 0; e < ne; ++e) {
+        W.lofs[e] = acc;
+        acc += W.ent[e][2] - W.ent[e][1];
+      }
+      W.lofs[ne] = acc;
+    }
+    sync();
+    for (int idx = t; idx < ne * ND; idx += NT) {
+      const int e = idx / ND, l = idx % ND;
+      const int64_t ro = (int64_t)W.rowr[e] * ND + l;
+      W.Wo[e][l] = w[ro];
+      W.Yo[e][l] = u[ro];
+      if constexpr (FACE) {
+        const int64_t rn = (int64_t)a.nb[(int64_t)W.rowr[e] * 2 * D + W.ent[e][3]] * ND + l;
+        W.Wn[e][l] = w[rn];
+        W.Yn[e][l] = u[rn];
+      }
+    }
+    sync();
+    const int total = W.lofs[ne];
+    for (int g = t; g < total; g += NT) {
+      int e = 0;
+      while (g >= W.lofs[e + 1]) ++e;
+      const int lid = W.ent[e][1] + (g - W.lofs[e]);
+      int ax = (a.line_info[lid] >> 16) & 0xf;
+      const int s = FACE ? W.ent[e][3] : -1;
+      if constexpr (FACE) {
+        const int nax = s >> 1;
+        ax = ax < nax ? ax : ax + 1;
+      }
+      const T* Wn = FACE ? &W.Wn[e][0] : nullptr;
+      const T* Yn = FACE ? &W.Yn[e][0] : nullptr;
+      if (ax == 0) line_dk<K, D, 0, FACE>(W.tab, a, lid, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
+      else if (ax == 1 || D == 2) line_dk<K, D, 1, FACE>(W.tab, a, lid, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
+      else if constexpr (D == 3) line_dk<K, D, 2, FACE>(W.tab, a, lid, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
+    }
     sync();
   }
 }
@@ -1363,20 +1661,55 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
   constexpr int NT = Shape<K, D>::NT;
   const int gi = (a.parts & 1) ? (int)std::min<int64_t>(a.n_inside, 1 << 20) : 0;
   const int gc = (a.parts & 2) ? (int)std::min<int64_t>(a.n_cut, 1 << 20) : 0;
+  if (adj && a.kappa == nullptr && ipow(K, D) <= 125) {
+    // A is symmetric: A^T w is the fast apply of w; dkappa from the
+    // evaluation kernels
+    DevArgs<T> b = a;
+    b.parts = 3;
+    hipError_t e = launch_kd<K, D, T>(b, x, nullptr, v, nullptr, false, s);
+    if (e != hipSuccess || dk == nullptr) return e;
+    if constexpr (ipow(K, D) <= 125) {
+      constexpr int CW = KronShape<K, D>::C, CF = FaceDkShape<K, D>::C;
+      if (a.n_inside > 0)
+        inside_dk_kernel<K, D, T><<<(int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20), 64, 0, s>>>(a, x, y, dk);
+      if (a.n_sfaces > 0)
+        face_dk_kernel<K, D, T><<<(int)std::min<int64_t>((a.n_sfaces + CF - 1) / CF, 1 << 20), 64, 0, s>>>(a, x, y, dk);
+      if (a.n_vbatch > 0)
+        cut_dk_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.vbatch, a.ventry,
+                                                                                   a.n_vbatch);
+      if (a.n_fbatch > 0)
+        cut_dk_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.fbatch, a.fentry,
+                                                                                  a.n_fbatch);
+    }
+    return hipGetLastError();
+  }
   if (!adj) {
+    bool fast_cut = false;
+    if constexpr (ipow(K, D) <= 125) fast_cut = a.kappa == nullptr;
     if (a.kappa == nullptr) {
       constexpr int CW = KronShape<K, D>::C;
       const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
-      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v);
+      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.inside, a.n_inside, 1);
     } else {
       if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
     }
-    // the Kronecker face pipeline of the register path assumes kappa = 1
-    bool fast_cut = false;
-    if constexpr (ipow(K, D) <= 125) fast_cut = a.kappa == nullptr;
     if (fast_cut) {
-      if constexpr (ipow(K, D) <= 125)
-        if (gc > 0) cut_line_kernel<K, D, T><<<gc, LineShape<K, D>::NT, 0, s>>>(a, x, v);
+      if constexpr (ipow(K, D) <= 125) {
+        // structured faces and ghost penalty of the cut cells (overwrites
+        // their rows), then the volume / interface lines and the cut-face
+        // lines are added
+        constexpr int CW = KronShape<K, D>::C;
+        const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
+        if (gs > 0) {
+          inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
+          if ((a.terms & 5) && a.n_vbatch > 0)
+            cut_batch_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.vbatch, a.ventry,
+                                                                                          a.n_vbatch);
+          if ((a.terms & 2) && a.n_fbatch > 0)
+            cut_batch_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.fbatch, a.fentry,
+                                                                                         a.n_fbatch);
+        }
+      }
     } else {
       if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
     }

@@ -98,6 +98,21 @@ def test_adjoint_and_dkappa_with_variable_kappa(torch, name):
         op.set_kappa(None)
 
 
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+def test_adjoint_and_dkappa_constant_kappa(torch, name):
+    """kappa = 1: A^T w and the per-point coefficient derivative."""
+    wl, ora, pl, op, u, w = _setup(name)
+    _say(f"[{name}] adjoint kappa=1")
+    atw, dk = op.apply_adjoint(torch.from_numpy(w).cuda(), torch.from_numpy(u).cuda())
+    assert _rel(atw.cpu().numpy(), ora.apply(w)) < TOL64
+    assert _rel(dk.cpu().numpy(), ora.dkappa(w, u)) < TOL64
+    atw32, dk32 = op.apply_adjoint(torch.from_numpy(w.astype(np.float32)).cuda(),
+                                   torch.from_numpy(u.astype(np.float32)).cuda())
+    w64, u64 = w.astype(np.float32).astype(np.float64), u.astype(np.float32).astype(np.float64)
+    assert _rel(atw32.cpu().numpy().astype(np.float64), ora.apply(w64)) < TOL32
+    assert _rel(dk32.cpu().numpy().astype(np.float64), ora.dkappa(w64, u64)) < TOL32
+
+
 def test_apply_is_repeatable_and_overwrites(torch):
     wl, ora, pl, op, u, w = _setup("ball3d_p3")
     ud = torch.from_numpy(u).cuda()
