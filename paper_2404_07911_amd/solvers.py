@@ -1,0 +1,214 @@
+"""Iterative solvers around the operator: conjugate gradients and the
+mixed-precision defect correction (FP32 inner solves, FP64 residual and
+update), written once against a small vector-operations interface.
+
+The paper solves with a preconditioned CG (Section 3.6); the
+preconditioners it uses live in external libraries and are not part of
+this package, so the drivers here are unpreconditioned.
+
+`DeviceOps` runs every vector operation in the HIP BLAS-1 kernels of
+libufem (dot products accumulate in float64 for both precisions and come
+back to the host as one scalar per call).  The drivers accept any apply
+callable and any ops object with the same methods.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+
+from . import _lib as L
+
+
+class DeviceOps:
+    """Vector operations on device tensors through the C ABI."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(f"cuda:{device}")
+        self._scalar = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    @staticmethod
+    def _prec(t):
+        import torch
+
+        return L.F64 if t.dtype == torch.float64 else L.F32
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def dot(self, x, y) -> float:
+        L.check(L.lib().ufem_dot(self._prec(x), x.numel(), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                 C.c_void_p(self._scalar.data_ptr()), self._stream()))
+        return float(self._scalar.item())
+
+    def axpby(self, a, x, b, y):
+        """y = a x + b y (in place)."""
+        L.check(L.lib().ufem_axpby(self._prec(y), y.numel(), float(a), C.c_void_p(x.data_ptr()), float(b),
+                                   C.c_void_p(y.data_ptr()), self._stream()))
+        return y
+
+    def copy(self, dst, src):
+        L.check(L.lib().ufem_cast(self._prec(src), self._prec(dst), src.numel(), C.c_void_p(src.data_ptr()),
+                                  C.c_void_p(dst.data_ptr()), self._stream()))
+        return dst
+
+    def cast(self, x, dtype):
+        out = self.torch.empty(x.numel(), dtype=dtype, device=x.device)
+        return self.copy(out, x)
+
+    def zeros_like(self, x, dtype=None):
+        return self.torch.zeros(x.numel(), dtype=dtype or x.dtype, device=x.device)
+
+    def empty_like(self, x, dtype=None):
+        return self.torch.empty(x.numel(), dtype=dtype or x.dtype, device=x.device)
+
+    def f32(self):
+        return self.torch.float32
+
+    def f64(self):
+        return self.torch.float64
+
+    def sync(self):
+        self.torch.cuda.synchronize()
+
+
+class HostOps:
+    """The same interface on numpy arrays (for the solver logic on the CPU)."""
+
+    def __init__(self):
+        import numpy as np
+
+        self.np = np
+
+    def dot(self, x, y) -> float:
+        return float(self.np.dot(x.astype(self.np.float64), y.astype(self.np.float64)))
+
+    def axpby(self, a, x, b, y):
+        y[:] = (a * x.astype(self.np.float64) + b * y.astype(self.np.float64)).astype(y.dtype)
+        return y
+
+    def copy(self, dst, src):
+        dst[:] = src.astype(dst.dtype)
+        return dst
+
+    def cast(self, x, dtype):
+        return x.astype(dtype)
+
+    def zeros_like(self, x, dtype=None):
+        return self.np.zeros(x.size, dtype=dtype or x.dtype)
+
+    def empty_like(self, x, dtype=None):
+        return self.np.empty(x.size, dtype=dtype or x.dtype)
+
+    def f32(self):
+        return self.np.float32
+
+    def f64(self):
+        return self.np.float64
+
+    def sync(self):
+        pass
+
+
+def cg(apply, b, x, ops, rtol=1e-10, maxiter=10000, rnorm0=None):
+    """Unpreconditioned CG for the SPD operator `apply`; x is updated in
+    place.  Returns (x, info) with iterations, relative residual (recursive),
+    convergence and breakdown flags (p^T A p <= 0)."""
+    r = ops.empty_like(b)
+    apply(x, r)
+    ops.axpby(1.0, b, -1.0, r)  # r = b - A x
+    p = ops.empty_like(b)
+    ops.copy(p, r)
+    Ap = ops.empty_like(b)
+    rr = ops.dot(r, r)
+    bnorm = math.sqrt(ops.dot(b, b)) if rnorm0 is None else rnorm0
+    info = {"iterations": 0, "converged": False, "breakdown": False, "rel_residual": None}
+    if bnorm == 0.0:
+        info.update(converged=True, rel_residual=0.0)
+        return x, info
+    target = (rtol * bnorm) ** 2
+    it = 0
+    while it < maxiter:
+        if rr <= target:
+            info["converged"] = True
+            break
+        apply(p, Ap)
+        pAp = ops.dot(p, Ap)
+        if not (pAp > 0.0) or not math.isfinite(pAp):
+            info["breakdown"] = True
+            break
+        alpha = rr / pAp
+        ops.axpby(alpha, p, 1.0, x)
+        ops.axpby(-alpha, Ap, 1.0, r)
+        rr_new = ops.dot(r, r)
+        beta = rr_new / rr
+        ops.axpby(1.0, r, beta, p)
+        rr = rr_new
+        it += 1
+    info["iterations"] = it
+    info["rel_residual"] = math.sqrt(max(rr, 0.0)) / bnorm
+    if rr <= target:
+        info["converged"] = True
+    return x, info
+
+
+def defect_correction(apply64, apply32, b, ops, tol=1e-10, inner_rtol=1e-4, max_outer=60, max_inner=20000,
+                      stagnation_factor=0.5, stagnation_window=3):
+    """Solve A u = b to ||b - A u|| <= tol ||b|| with the residual b - A u
+    and the update u += d in FP64 and the correction A d = r solved by CG in
+    FP32 (the residual is scaled to unit norm before the cast).
+
+    Returns (u, info): outer steps, total inner iterations, relative residual
+    history (FP64), and a stagnation flag (no reduction by
+    `stagnation_factor` over `stagnation_window` outer steps)."""
+    u = ops.zeros_like(b)
+    r = ops.empty_like(b)
+    ops.copy(r, b)
+    bnorm = math.sqrt(ops.dot(b, b))
+    hist = []
+    inner_total = 0
+    info = {"outer": 0, "inner_iterations": 0, "converged": False, "stagnated": False, "history": hist,
+            "inner_breakdown": False}
+    if bnorm == 0.0:
+        info["converged"] = True
+        return u, info
+    r32 = ops.empty_like(b, ops.f32())
+    d32 = ops.empty_like(b, ops.f32())
+    d64 = ops.empty_like(b)
+    for k in range(max_outer + 1):
+        rnorm = math.sqrt(ops.dot(r, r))
+        hist.append(rnorm / bnorm)
+        if rnorm <= tol * bnorm:
+            info["converged"] = True
+            break
+        if len(hist) > stagnation_window and hist[-1] > stagnation_factor * hist[-1 - stagnation_window]:
+            info["stagnated"] = True
+            break
+        if k == max_outer:
+            break
+        # r32 = r / ||r||
+        ops.copy(r32, r)
+        ops.axpby(0.0, r32, 1.0 / rnorm, r32)
+        d32 = ops.zeros_like(r32)
+        _, ii = cg(apply32, r32, d32, ops, rtol=inner_rtol, maxiter=max_inner)
+        inner_total += ii["iterations"]
+        info["inner_breakdown"] |= ii["breakdown"]
+        ops.copy(d64, d32)
+        ops.axpby(rnorm, d64, 1.0, u)  # u += ||r|| d
+        apply64(u, r)
+        ops.axpby(1.0, b, -1.0, r)  # r = b - A u
+        info["outer"] = k + 1
+    info["inner_iterations"] = inner_total
+    info["rel_residual"] = hist[-1]
+    return u, info
+
+
+def timed(fn, ops):
+    ops.sync()
+    t0 = time.perf_counter()
+    out = fn()
+    ops.sync()
+    return out, time.perf_counter() - t0

@@ -1,0 +1,129 @@
+"""GPU tests of the solve and of the differentiable operator:
+FP32-inner / FP64-outer defect correction and plain FP64 CG to 1e-10 (the
+residual re-checked with the oracle), and the autograd wrapper against the
+oracle's A^T r and dL/dkappa, plus central finite differences in kappa."""
+import sys
+
+import numpy as np
+import pytest
+
+import ufem_inputs as ui
+from oracle.operator import ALL
+from tests.helpers import oracle_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ball(torch):
+    from paper_2404_07911_amd import Operator, Plan, Problem
+
+    wl, rng = ui.ball3d(5, n=10, degree=2)
+    ora = oracle_for(wl)
+    op = Operator(Plan(Problem.from_workload(wl)))
+    ustar = ui.uniform_vector(rng, ora.n_dofs)
+    return wl, ora, op, ustar
+
+
+def test_defect_correction_and_fp64_cg(torch, ball):
+    from paper_2404_07911_amd.solvers import DeviceOps, cg, defect_correction
+
+    wl, ora, op, ustar = ball
+    ops = DeviceOps(0)
+    us = torch.from_numpy(ustar).cuda()
+    b = op.apply(us)
+
+    def a64(x, out):
+        op.apply(x, out)
+
+    def a32(x, out):
+        op.apply(x, out)
+
+    _say("[solve] defect correction")
+    u, info = defect_correction(a64, a32, b, ops, tol=1e-10, inner_rtol=1e-4)
+    assert info["converged"], info
+    bh = b.cpu().numpy()
+    res = np.linalg.norm(bh - ora.apply(u.cpu().numpy())) / np.linalg.norm(bh)
+    assert res < 2e-10, res
+    _say("[solve] fp64 cg")
+    x = torch.zeros_like(b)
+    x, info64 = cg(a64, b, x, ops, rtol=1e-10, maxiter=20000)
+    assert info64["converged"], info64
+    res64 = np.linalg.norm(bh - ora.apply(x.cpu().numpy())) / np.linalg.norm(bh)
+    assert res64 < 2e-10, res64
+
+
+def test_autograd_matches_oracle_gradients(torch, ball):
+    from paper_2404_07911_amd import ufem_apply
+
+    wl, ora, op, ustar = ball
+    rng = np.random.default_rng(9)
+    bvec = rng.uniform(-1, 1, ora.n_dofs)
+    kap = ui.kappa_field(ora.qp_physical_points())
+    u = torch.from_numpy(ustar).cuda().requires_grad_(True)
+    k = torch.from_numpy(kap).cuda().requires_grad_(True)
+    bt = torch.from_numpy(bvec).cuda()
+    try:
+        v = ufem_apply(u, k, op)
+        loss = 0.5 * ((v - bt) ** 2).sum()
+        loss.backward()
+        r = ora.apply(ustar, ALL, kap) - bvec
+        gu = ora.apply(r, ALL, kap)
+        gk = ora.dkappa(r, ustar)
+        ru = np.abs(u.grad.cpu().numpy() - gu).max() / np.abs(gu).max()
+        rk = np.abs(k.grad.cpu().numpy() - gk).max() / np.abs(gk).max()
+        assert ru < 1e-12 and rk < 1e-12, (ru, rk)
+    finally:
+        op.set_kappa(None)
+
+
+def test_dkappa_central_differences_degree4(torch):
+    """kappa workload in miniature (degree 4): dL/dkappa . delta against
+    (L(kappa + h delta) - L(kappa - h delta)) / 2h, all on the GPU operator.
+    L is quadratic in kappa, so the central difference has no truncation
+    error: with h = 1e-6 only the rounding of L remains (bounded by a few
+    eps |L| / h), with h = 1e-2 the agreement is to 1e-9."""
+    from paper_2404_07911_amd import Operator, Plan, Problem
+
+    wl, rng = ui.kappa3d(0, n=8, degree=4)
+    pl = Plan(Problem.from_workload(wl))
+    op = Operator(pl)
+    xyz = pl.qp()[0]
+    kap = torch.from_numpy(ui.kappa_field(xyz)).cuda()
+    u = torch.from_numpy(ui.uniform_vector(rng, pl.info["n_dofs"])).cuda()
+    b = torch.from_numpy(ui.uniform_vector(rng, pl.info["n_dofs"])).cuda()
+    delta = torch.from_numpy(rng.uniform(-1, 1, pl.info["n_qp"])).cuda()
+
+    def loss(k):
+        op.set_kappa(k)
+        v = op.apply(u)
+        return 0.5 * float(((v - b) ** 2).sum())
+
+    try:
+        op.set_kappa(kap)
+        r = op.apply(u) - b
+        _, dk = op.apply_adjoint(r.contiguous(), u)
+        g = float((dk * delta).sum())
+        L0 = loss(kap)
+        h = 1e-6
+        fd = (loss(kap + h * delta) - loss(kap - h * delta)) / (2 * h)
+        assert abs(fd - g) < 8 * 2.3e-16 * L0 / h + 1e-9 * abs(g), (fd, g, L0)
+        h = 1e-2
+        fd = (loss(kap + h * delta) - loss(kap - h * delta)) / (2 * h)
+        assert abs(fd - g) < 1e-9 * abs(g) + 8 * 2.3e-16 * L0 / h, (fd, g, L0)
+    finally:
+        op.set_kappa(None)
