@@ -45,34 +45,45 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def model(info, dim, p, s):
-    """Algorithmic bytes per kernel launch and model FLOPs of one apply.
+STAGES = {1: "inside", 2: "cut_structured", 4: "cut_lines", 8: "cut_face_lines"}
+STAGE_KERNELS = {
+    "inside": "inside_kron_kernel (inside cells)",
+    "cut_structured": "inside_kron_kernel (cut cells, structured faces and ghost penalty)",
+    "cut_lines": "cut_batch_kernel<FACE=false> (volume and interface lines)",
+    "cut_face_lines": "cut_batch_kernel<FACE=true> (cut-face lines)",
+}
 
-    Bytes (s = bytes per value): read u and write v once per DoF (2 s per DoF),
-    the cut-cell quadrature data once (volume point: dim coordinates and a
-    weight; interface point: coordinates, weight, normal; cut-face point:
-    dim - 1 in-face coordinates and a weight) and the int32/int64 index
-    tables.  FLOPs: the paper's operation counts (Section 5.1) for 3D:
-    24 k^4 per structured cell, 56 k^3 per structured face (both sides,
-    evaluation and integration), 4 (2k^3 + 3k^2 + 4k) per unstructured cell or
-    interface point, 8 (k^3 + n_q (3k^2 + 4k)) per cut face, and 28 k^3 per
+
+def model(info, dim, p, s):
+    """Algorithmic bytes per kernel stage and model FLOPs of one apply.
+
+    Bytes (s = bytes per value) count what a stage must move at the least:
+    the rows of u it reads and of v it writes for its own cells (inside: read
+    u, write v; cut structured: read u, write v; the two line stages add to
+    v, so read u, read and write v), and the quadrature data of the cut cells
+    (volume point: dim coordinates and a weight; interface point: dim
+    coordinates, a weight and dim normal components; cut-face point: dim - 1
+    in-face coordinates and a weight).  Index tables are not counted.
+    FLOPs: the paper's operation counts (Section 5.1) for 3D: 24 k^4 per
+    structured cell, 56 k^3 per structured face (both sides, evaluation and
+    integration), 4 (2k^3 + 3k^2 + 4k) per unstructured cell or interface
+    point, 8 (k^3 + n_q (3k^2 + 4k)) per cut face, and 28 k^3 per
     ghost-penalty derivative order and face.
     """
     k = p + 1
     nd = k**dim
-    S = 2 * dim
     seg = info["seg"]
     n_vol = seg[2] - seg[1]
     n_fcut = seg[4] - seg[3]
     n_surf = seg[5] - seg[4]
-    b_inside = info["n_inside"] * (nd * 2 * s + 4 + 4 * S + 4)
-    b_cut = (
-        info["n_cut"] * (nd * 2 * s + 4 + 4 + 4 * S * 2 + 4 + 16)
-        + n_vol * (dim + 1) * s
-        + n_surf * (2 * dim + 1) * s
-        + n_fcut * dim * s
-        + info["n_faces_cut"] * 12
-    )
+    b = {
+        "inside": info["n_inside"] * nd * 2 * s,
+        "cut_structured": info["n_cut"] * nd * 2 * s,
+        "cut_lines": info["n_cut"] * nd * 3 * s + n_vol * (dim + 1) * s + n_surf * (2 * dim + 1) * s,
+        "cut_face_lines": info["n_cut"] * nd * 3 * s + n_fcut * dim * s,
+    }
+    # the whole apply: u read and v written once per DoF, plus the point data
+    b["total"] = info["n_dofs"] * 2 * s + n_vol * (dim + 1) * s + n_surf * (2 * dim + 1) * s + n_fcut * dim * s
     flops = None
     if dim == 3:
         flops = (
@@ -82,7 +93,7 @@ def model(info, dim, p, s):
             + (n_vol + n_surf) * 4 * (2 * k**3 + 3 * k**2 + 4 * k)
             + 8 * (info["n_faces_cut"] * k**3 + n_fcut * (3 * k**2 + 4 * k))
         )
-    return {"inside": b_inside, "cut": b_cut, "total": b_inside + b_cut}, flops
+    return b, flops
 
 
 def load_counters(kernel_key):
@@ -268,30 +279,30 @@ def main(argv=None):
     DK = torch.empty(info["n_qp"], dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
+    # one step: the FP64 apply and the FP32 apply stage by stage (each stage
+    # one kernel, bracketed by events on the library's stream), then the FP64
+    # adjoint pass
+    NEV = 10
+
     def step(i, ev=None):
         j = i % npairs
+        k = 0
+        for U, V in ((U64[j], V64[j]), (U32[j], V32[j])):
+            for part in STAGES:
+                if ev is not None:
+                    ev[k].record(stream)
+                k += 1
+                op.apply_part(part, U, V)
         if ev is not None:
-            ev[0].record(stream)
-        op.apply_part(1, U64[j], V64[j])
-        if ev is not None:
-            ev[1].record(stream)
-        op.apply_part(2, U64[j], V64[j])
-        if ev is not None:
-            ev[2].record(stream)
-        op.apply_part(1, U32[j], V32[j])
-        if ev is not None:
-            ev[3].record(stream)
-        op.apply_part(2, U32[j], V32[j])
-        if ev is not None:
-            ev[4].record(stream)
+            ev[8].record(stream)
         op.apply_adjoint(W64, U64[j], ATW, DK)
         if ev is not None:
-            ev[5].record(stream)
+            ev[9].record(stream)
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(NEV)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -302,12 +313,13 @@ def main(argv=None):
     def mean_ms(a, b):
         return float(np.mean([e[a].elapsed_time(e[b]) for e in evs]))
 
-    k64_in, k64_cut = mean_ms(0, 1), mean_ms(1, 2)
-    k32_in, k32_cut = mean_ms(2, 3), mean_ms(3, 4)
-    adj = mean_ms(4, 5)
-    step_ms = mean_ms(0, 5)
-    t64 = (k64_in + k64_cut) * 1e-3
-    t32 = (k32_in + k32_cut) * 1e-3
+    names = list(STAGES.values())
+    ms64 = {nm: mean_ms(q, q + 1) for q, nm in enumerate(names)}
+    ms32 = {nm: mean_ms(4 + q, 4 + q + 1) for q, nm in enumerate(names)}
+    adj = mean_ms(8, 9)
+    step_ms = mean_ms(0, 9)
+    t64 = mean_ms(0, 4) * 1e-3
+    t32 = mean_ms(4, 8) * 1e-3
     tadj = adj * 1e-3
 
     # correctness spot check of the timed FP64 result against a fresh apply
@@ -317,14 +329,14 @@ def main(argv=None):
 
     bytes64, flops = model(info, wl.dim, wl.degree, 8)
     bytes32, _ = model(info, wl.dim, wl.degree, 4)
-    dom = "inside" if k64_in >= k64_cut else "cut"
-    dom_ms = k64_in if dom == "inside" else k64_cut
+    dom = max(ms64, key=ms64.get)
+    dom_ms = ms64[dom]
     achieved = bytes64[dom] / (dom_ms * 1e-3) / 1e9
     ctr = load_counters(f"{args.workload}_p{wl.degree}_n{wl.n}_{dom}_f64")
     traffic = ctr["hbm_bytes_per_launch"] if ctr else None
     roofline = {
         "bound": "hbm",
-        "kernel": f"{dom}_kernel<K={wl.degree + 1},D={wl.dim},double>",
+        "kernel": f"{STAGE_KERNELS[dom]}, K={wl.degree + 1}, D={wl.dim}, double",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -365,7 +377,9 @@ def main(argv=None):
         "fp32_speedup": t64 / t32,
         "adjoint_value": n / tadj,
         "adjoint_ms": tadj * 1e3,
-        "kernels_ms": {"inside_f64": k64_in, "cut_f64": k64_cut, "inside_f32": k32_in, "cut_f32": k32_cut, "adjoint_f64": adj},
+        "kernels_ms": {**{f"{nm}_f64": ms64[nm] for nm in names}, **{f"{nm}_f32": ms32[nm] for nm in names},
+                       "adjoint_f64": adj},
+        "kernels_hbm_frac_f64": {nm: bytes64[nm] / (ms64[nm] * 1e-3) / 1e9 / HBM_PEAK_GBS for nm in names},
         "apply_hbm_frac_f64": apply_gbs / HBM_PEAK_GBS,
         "apply_hbm_frac_f32": bytes32["total"] / t32 / 1e9 / HBM_PEAK_GBS,
         "model_gflop_per_apply": flops / 1e9 if flops else None,

@@ -59,6 +59,22 @@ enum {
  * accumulation is in this precision. */
 enum { UFEM_F64 = 0, UFEM_F32 = 1 };
 
+/* Kernel stages of one apply (ufem_apply_part).  Stage 1 writes the rows of
+ * inside cells.  Stage 2 writes the rows of cut cells: with kappa = 1 and
+ * degree such that (p+1)^dim <= 125 only their structured-face and
+ * ghost-penalty terms (sum factorisation), otherwise the whole cut cell.
+ * Stages 4 and 8 add the dimension-reduction volume and interface lines and
+ * the cut-face lines to the rows stage 2 wrote (no work where stage 2 already
+ * did the whole cell). */
+enum {
+  UFEM_PART_INSIDE = 1,
+  UFEM_PART_CUT_STRUCTURED = 2,
+  UFEM_PART_CUT_LINES = 4,
+  UFEM_PART_CUT_FACE_LINES = 8,
+  UFEM_PART_CUT = 14,
+  UFEM_PART_ALL = 15
+};
+
 typedef struct ufem_plan ufem_plan; /* host-side plan (no GPU) */
 typedef struct ufem_op ufem_op;     /* device-side operator */
 
@@ -148,11 +164,13 @@ int ufem_set_kappa(ufem_op* op, int32_t precision, const void* kappa, void* stre
  * allocates nothing. */
 int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* stream);
 
-/* The two kernels of ufem_apply one at a time, for per-kernel timing:
- * part 1 writes the rows of inside cells (structured cell and face
- * quadrature), part 2 the rows of cut cells (dimension-reduction quadrature,
- * interface, cut and structured faces); part 3 is ufem_apply.  Rows of the
- * other class are left untouched. */
+/* The kernel stages of ufem_apply (UFEM_PART_* bits, any non-empty mask),
+ * for per-kernel timing; UFEM_PART_ALL is ufem_apply.  Stages run in the
+ * order 1, 2, 4, 8 on `stream`; rows of the cells a mask does not cover are
+ * left untouched, and stages 4 and 8 add to v, so the rows of cut cells are
+ * A u only when stages 2, 4 and 8 run after one another (in one call or in
+ * consecutive calls with the same u and v).  EINVAL for an empty or unknown
+ * mask. */
 int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u, void* v, void* stream);
 
 /* Adjoint pass for L(kappa, u) with residual weight w:

@@ -9,7 +9,8 @@ built: there is no fallback path.  (`python -m paper_2404_07911_amd.build`
 compiles it.)
 """
 from . import _lib
-from ._lib import F32, F64, TERM_ALL, TERM_GHOST, TERM_NITSCHE, TERM_SIPG, TERM_VOLUME, UfemError
+from ._lib import (F32, F64, PART_ALL, PART_CUT, PART_CUT_FACE_LINES, PART_CUT_LINES, PART_CUT_STRUCTURED,
+                   PART_INSIDE, TERM_ALL, TERM_GHOST, TERM_NITSCHE, TERM_SIPG, TERM_VOLUME, UfemError)
 from .ufem import Operator, Plan, Problem, ufem_apply
 
 __all__ = [
@@ -25,4 +26,10 @@ __all__ = [
     "TERM_SIPG",
     "TERM_NITSCHE",
     "TERM_GHOST",
+    "PART_INSIDE",
+    "PART_CUT_STRUCTURED",
+    "PART_CUT_LINES",
+    "PART_CUT_FACE_LINES",
+    "PART_CUT",
+    "PART_ALL",
 ]

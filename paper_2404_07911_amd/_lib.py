@@ -10,6 +10,8 @@ LIB_PATH = os.path.join(HERE, "libufem.so")
 UFEM_OK, UFEM_EINVAL, UFEM_ENOMEM, UFEM_EHIP, UFEM_EUNSUPPORTED, UFEM_ESTATE = 0, -1, -2, -3, -4, -5
 TERM_VOLUME, TERM_SIPG, TERM_NITSCHE, TERM_GHOST, TERM_ALL = 1, 2, 4, 8, 15
 F64, F32 = 0, 1
+PART_INSIDE, PART_CUT_STRUCTURED, PART_CUT_LINES, PART_CUT_FACE_LINES = 1, 2, 4, 8
+PART_CUT, PART_ALL = 14, 15
 
 
 class ufem_problem(C.Structure):

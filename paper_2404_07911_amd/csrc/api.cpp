@@ -121,7 +121,7 @@ struct ufem_op {
   int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
   int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
           *line_info = nullptr, *cell_desc = nullptr, *vbatch = nullptr, *ventry = nullptr, *fbatch = nullptr,
-          *fentry = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
+          *fentry = nullptr, *vline = nullptr, *fline = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0;
   // per-precision data
   struct Prec {
@@ -214,6 +214,8 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.ventry = ventry;
   a.fbatch = fbatch;
   a.fentry = fentry;
+  a.vline = vline;
+  a.fline = fline;
   a.n_vbatch = n_vbatch;
   a.n_fbatch = n_fbatch;
   a.sf_bm = sf_bm;
@@ -239,7 +241,7 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.tau = (T)P.tau;
   a.gamma = (T)P.gamma;
   a.terms = terms;
-  a.parts = 3;
+  a.parts = 15;
   return a;
 }
 
@@ -449,39 +451,67 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
     // line batches for the cut-cell kernels: cells (most work first) packed
     // into waves of at most 64 lines; a cell with more lines gets a wave of
-    // its own
-    const int me = P.nd() <= 64 ? 16 : 8;
-    auto make_batches = [&](bool face, std::vector<int32_t>& batches, std::vector<int32_t>& entries) {
+    // its own.  Per batch line descriptors (first point, line info | entry
+    // << 24), the lines of each entry ordered by cell axis.
+    bool batch_overflow = false;
+    auto make_batches = [&](bool face, std::vector<int32_t>& batches, std::vector<int32_t>& entries,
+                            std::vector<int32_t>& blines) {
+      const int me = ufem::batch_max_entries((int)P.nd(), face);
       int cur_lines = 0, cur_n = 0, first = 0;
       auto close = [&]() {
         if (cur_n > 0) {
           batches.push_back(first);
           batches.push_back(cur_n);
+          batches.push_back(cur_lines);
+          batches.push_back((int32_t)(blines.size() / 2) - cur_lines);
         }
         first = (int)(entries.size() / 4);
         cur_lines = 0;
         cur_n = 0;
       };
       for (int32_t ci : order) {
-        std::vector<int32_t> ce;
+        const int32_t r = P.cut[ci];
+        std::vector<int32_t> ce;  // (first line, end line, slot, neighbour)
         if (!face) {
           const int32_t lb = (int32_t)P.cell_line_off[ci], le = (int32_t)P.cell_line_off[ci + 1];
-          if (le > lb) ce.insert(ce.end(), {ci, lb, le, -1});
+          if (le > lb) ce.insert(ce.end(), {lb, le, 15, -1});
         } else {
           for (int sl = 0; sl < S; ++sl) {
-            int32_t fi = P.slot_face[(size_t)P.cut[ci] * S + sl];
+            int32_t fi = P.slot_face[(size_t)r * S + sl];
             if (fi < 0 || P.faces[fi].kind != ufem::kFaceCut || fle[fi] <= flb[fi]) continue;
-            ce.insert(ce.end(), {ci, flb[fi], fle[fi], sl});
+            ce.insert(ce.end(), {flb[fi], fle[fi], sl, nb[(size_t)r * S + sl]});
           }
         }
         if (ce.empty()) continue;
         int nl = 0, n_e = (int)ce.size() / 4;
-        for (int e = 0; e < n_e; ++e) nl += ce[4 * e + 2] - ce[4 * e + 1];
-        if (cur_n > 0 && (cur_lines + nl > 64 || cur_n + n_e > me)) close();
-        entries.insert(entries.end(), ce.begin(), ce.end());
-        cur_lines += nl;
+        for (int e = 0; e < n_e; ++e) nl += ce[4 * e + 1] - ce[4 * e];
+        if (cur_n > 0 && (cur_lines + nl > ufem::kBatchLines || cur_n + n_e > me)) close();
+        if (n_e > me || cur_lines + nl >= (1 << ufem::kBatchOffsetBits)) {
+          batch_overflow = true;
+          return;
+        }
+        for (int e = 0; e < n_e; ++e) {
+          const int32_t lb = ce[4 * e], le = ce[4 * e + 1], sl = ce[4 * e + 2];
+          const int nax = sl >> 1;
+          int cnt[3] = {0, 0, 0};
+          for (int ax = 0; ax < P.dim; ++ax)
+            for (int32_t l = lb; l < le; ++l) {
+              int la = P.line_axis[l];
+              if (face) la = la < nax ? la : la + 1;  // in-face axis -> cell axis
+              if (la != ax) continue;
+              blines.push_back((int32_t)P.line_first[l]);
+              blines.push_back(linfo[l] | ((cur_n + e) << 24));
+              ++cnt[ax];
+            }
+          if (cnt[0] > 0xffff || cnt[1] > 0xffff) {
+            batch_overflow = true;
+            return;
+          }
+          entries.insert(entries.end(), {r, cnt[0] | (cnt[1] << 16), cur_lines | (sl << ufem::kBatchOffsetBits), ce[4 * e + 3]});
+          cur_lines += le - lb;
+        }
         cur_n += n_e;
-        if (cur_lines >= 64) close();
+        if (cur_lines >= ufem::kBatchLines) close();
       }
       close();
     };
@@ -493,11 +523,15 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         sax.push_back(f.axis);
       }
     op->n_sfaces = (int32_t)sbm.size();
-    std::vector<int32_t> vb, ve, fb, fe;
-    make_batches(false, vb, ve);
-    make_batches(true, fb, fe);
-    op->n_vbatch = (int32_t)(vb.size() / 2);
-    op->n_fbatch = (int32_t)(fb.size() / 2);
+    std::vector<int32_t> vb, ve, vl, fb, fe, fl;
+    make_batches(false, vb, ve, vl);
+    make_batches(true, fb, fe, fl);
+    if (batch_overflow) {
+      delete op;
+      return fail(UFEM_EUNSUPPORTED, "ufem_setup: a cut cell has more lines or cut faces than one line batch holds");
+    }
+    op->n_vbatch = (int32_t)(vb.size() / 4);
+    op->n_fbatch = (int32_t)(fb.size() / 4);
     int rc;
     if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->cut_order, order)) ||
         (rc = op->upload((void**)&op->cut_rank, P.cut)) || (rc = op->upload((void**)&op->nb, nb)) ||
@@ -509,6 +543,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc)) ||
         (rc = op->upload((void**)&op->vbatch, vb)) || (rc = op->upload((void**)&op->ventry, ve)) ||
         (rc = op->upload((void**)&op->fbatch, fb)) || (rc = op->upload((void**)&op->fentry, fe)) ||
+        (rc = op->upload((void**)&op->vline, vl)) || (rc = op->upload((void**)&op->fline, fl)) ||
         (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||
         (rc = op->upload((void**)&op->sf_ax, sax))) {
       delete op;
@@ -569,12 +604,12 @@ static bool overlap2(const void* a, size_t na, const void* b, size_t nb) {
 static bool overlap(const void* a, const void* b, size_t n) { return overlap2(a, n, b, n); }
 
 int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* stream) {
-  return ufem_apply_part(op, precision, 3, u, v, stream);
+  return ufem_apply_part(op, precision, UFEM_PART_ALL, u, v, stream);
 }
 
 int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u, void* v, void* stream) {
   if (!op || !u || !v) return fail(UFEM_EINVAL, "ufem_apply: null argument");
-  if (part < 1 || part > 3) return fail(UFEM_EINVAL, "ufem_apply_part: part must be 1, 2 or 3");
+  if (part < 1 || part > UFEM_PART_ALL) return fail(UFEM_EINVAL, "ufem_apply_part: part must be a non-empty mask of UFEM_PART_* bits");
   if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_apply: bad precision");
   const size_t bytes = (size_t)op->P.n_dofs() * (precision == UFEM_F64 ? 8 : 4);
   if (overlap(u, v, bytes)) return fail(UFEM_EINVAL, "ufem_apply: u and v overlap");

@@ -25,6 +25,17 @@ constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
 //   M [K*K]   1D mass matrix of the GLL Lagrange basis (exact: Gauss rule)
 //   KS[K*K]   1D stiffness matrix of the GLL Lagrange basis
 //   DS[K*K]   DS[q*K+i] = L_i'(g_q), GLL basis derivative at the Gauss points
+// Line batches of the cut-cell kernels.  Batch b = (first entry, entries,
+// lines, first line descriptor).  Entry = (active rank of the cell, lines
+// along axis 0 | lines along axis 1 << 16, offset of the entry's first line
+// in the batch | slot << 24, active rank of the neighbour across the slot or
+// -1).  Line descriptor = (first point, count | axis << 16 | kind << 20 |
+// entry << 24); the lines of an entry are consecutive and ordered by cell
+// axis.  Entries of one cell are consecutive and in one batch.
+constexpr __host__ __device__ int batch_max_entries(int, bool) { return 8; }
+constexpr int kBatchLines = 64;        // lines per round (one per lane)
+constexpr int kBatchOffsetBits = 24;   // bits of the in-batch line offset
+
 struct TabOff {
   static __host__ __device__ constexpr int S(int) { return 0; }
   static __host__ __device__ constexpr int DG(int K) { return K * K; }
@@ -57,13 +68,15 @@ struct DevArgs {
   const int32_t* line_first;     // first point of a line
   const int32_t* line_info;      // count | axis << 16 | kind << 20
   const int32_t* cell_desc;      // [n_cut * 24] line segments of each cut cell
-  // line batches: batch b covers entries [vbatch[2b], +vbatch[2b+1]); an
-  // entry is (cut index, first line, end line, slot) -- slot -1 for the
-  // volume / interface lines of a cell, the face slot for cut-face lines
+  // line batches (layout above): volume / interface lines of cut cells
+  // (slot 15, no neighbour) and cut-face lines (one entry per cut face of a
+  // cut cell, slot of the face)
   const int32_t* vbatch;
   const int32_t* ventry;
   const int32_t* fbatch;
   const int32_t* fentry;
+  const int32_t* vline;  // line descriptors, pairs
+  const int32_t* fline;
   int32_t n_vbatch, n_fbatch;
   // structured SIPG faces (kappa order): ranks of the lower / upper cell, axis
   const int32_t* sf_bm;
@@ -86,7 +99,9 @@ struct DevArgs {
   T hs;                      // h^(dim - 2)
   T tau, gamma;
   int32_t terms;             // term mask
-  int32_t parts;             // 1: inside-cell kernel, 2: cut-cell kernel
+  int32_t parts;             // stage bits: 1 inside cells, 2 cut cells (whole cell on the
+                             // quadrature path, structured faces on the line path), 4 cut
+                             // volume and interface lines, 8 cut-face lines
 };
 
 // Launchers: the per-dimension operator kernels live in op_<prec>_<dim>d.hip,

@@ -942,9 +942,13 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
 template <int K, int D>
 struct LineShape {
   static constexpr int ND = ipow(K, D);
-  static constexpr int NF = ipow(K, D - 1);
   static constexpr int NT = 64;
-  static constexpr int RS = D == 3 ? 7 * K + 1 : 4 * K + 1;  // record size
+  // line record, K-vectors [V1 | dV1 | V2 | dV2 | D0 | D1 | D2] (3D) or
+  // [V1 | dV1 | D0 | D1] (2D): the line's test-function coefficient of DoF
+  // (i_KA, i_O1, i_O2) is V2 (V1 D0 + dV1 D1) + V1 dV2 D2
+  static constexpr int RS = D == 3 ? 7 * K : 4 * K;
+  static constexpr int V1 = 0, DV1 = K, V2 = 2 * K, DV2 = 3 * K, D0 = D == 3 ? 4 * K : 2 * K,
+                       D1 = D0 + K, D2 = D0 + 2 * K;
 };
 
 // columns along axis KA of the DoF tensor u contracted with (V1, dV1) over
@@ -958,8 +962,9 @@ __device__ __forceinline__ void line_columns(const T* u, const T* V1, const T* d
   constexpr int SK = ipow(K, KA), S1 = ipow(K, O1), S2 = D == 3 ? ipow(K, O2) : 0;
 #pragma unroll
   for (int lk = 0; lk < K; ++lk) {
-    // one layer of loads at a time keeps the register footprint at K^2
-    __builtin_amdgcn_sched_barrier(0);
+    // one layer of loads at a time keeps the register footprint at K^2: the
+    // empty asm at the end of a layer needs the layer's sums and keeps the
+    // next layer's LDS reads behind it
     T a0 = 0, a1 = 0, a2 = 0;
     if constexpr (D == 3) {
 #pragma unroll
@@ -983,112 +988,88 @@ __device__ __forceinline__ void line_columns(const T* u, const T* V1, const T* d
         a1 += dV1[aa] * uu;
       }
     }
+    asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2)::"memory");
     c0[lk] = a0;
     c1[lk] = a1;
     c2[lk] = a2;
   }
 }
 
-// one line of points: evaluate, apply the point flux, integrate along the
-// line; writes the line record
-template <int K, int D, int KA, bool FACE, typename T>
-__device__ __forceinline__ void line_work(const T* tab, const DevArgs<T>& a, int lid, int slot, const T* Uo,
-                                          const T* Un, T* rec) {
+// store a line record (layout of LineShape)
+template <int K, int D, typename T>
+__device__ __forceinline__ void line_record(const T* V1, const T* dV1, const T* V2, const T* dV2, const T* D0,
+                                            const T* D1, const T* D2, T* R) {
+  using LS = LineShape<K, D>;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    R[LS::V1 + i] = V1[i];
+    R[LS::DV1 + i] = dV1[i];
+    R[LS::D0 + i] = D0[i];
+    R[LS::D1 + i] = D1[i];
+    if constexpr (D == 3) {
+      R[LS::V2 + i] = V2[i];
+      R[LS::DV2 + i] = dV2[i];
+      R[LS::D2 + i] = D2[i];
+    }
+  }
+}
+
+// one volume or interface line of points along cell axis KA: evaluate,
+// apply the point flux, integrate along the line; leaves the line record in
+// R.  info / p0: the line descriptor (count | axis << 16 | kind << 20, first
+// point)
+template <int K, int D, int KA, typename T>
+__device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a, int info, int p0, const T* Uo,
+                                               T* R) {
   constexpr int O1 = KA == 0 ? 1 : 0;
   constexpr int O2 = KA == 2 ? 1 : 2;
+  constexpr int PB = 4;  // points whose data is loaded in one round
   const T* Xn = tab + TabOff::X(K);
   const T* ID = tab + TabOff::ID(K);
-  const int info = a.line_info[lid];
   const int n = info & 0xffff;
-  const int kind = FACE ? 2 : ((info >> 20) & 0xf);
-  const int p0 = a.line_first[lid];
-  T V1[K], dV1[K], V2[K], dV2[K];
-  T V1n[K], dV1n[K], V2n[K], dV2n[K];
-  const T* px;
-  int64_t stride;
-  int64_t kbase;
-  const T* pw;
-  const T* En = nullptr;
-  const T* Eo = nullptr;
-  T sigma = 1;
-  int nax = -1;  // face normal axis
-  if (kind == 2) {
-    const int side = slot & 1;
-    nax = slot >> 1;
-    Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-    En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-    sigma = side ? T(1) : T(-1);
-    px = a.fcut_x;
-    stride = a.n_fcut;
-    pw = a.fcut_w;
-    kbase = a.seg[3];
-  } else if (kind == 1) {
-    px = a.surf_x;
-    stride = a.n_surf;
-    pw = a.surf_w;
-    kbase = a.seg[4];
-  } else {
-    px = a.vol_x;
-    stride = a.n_vol;
-    pw = a.vol_w;
-    kbase = a.seg[1];
-  }
-  // coordinate of the point along cell axis ax (faces store in-face axes)
-  auto coord = [&](int64_t q, int ax) -> T {
-    if (kind == 2) {
-      const int fa = ax < nax ? ax : ax - 1;
-      return px[fa * stride + q];
-    }
-    return px[ax * stride + q];
-  };
-  // fixed-axis basis; the face normal axis takes the end-point data
-  if (kind == 2 && O1 == nax) {
-#pragma unroll
-    for (int i = 0; i < K; ++i) { V1[i] = Eo[i]; dV1[i] = Eo[K + i]; V1n[i] = En[i]; dV1n[i] = En[K + i]; }
-  } else {
-    lagrange1d<K>(Xn, ID, coord(p0, O1), V1, dV1);
-#pragma unroll
-    for (int i = 0; i < K; ++i) { V1n[i] = V1[i]; dV1n[i] = dV1[i]; }
-  }
-  if constexpr (D == 3) {
-    if (kind == 2 && O2 == nax) {
-#pragma unroll
-      for (int i = 0; i < K; ++i) { V2[i] = Eo[i]; dV2[i] = Eo[K + i]; V2n[i] = En[i]; dV2n[i] = En[K + i]; }
-    } else {
-      lagrange1d<K>(Xn, ID, coord(p0, O2), V2, dV2);
-#pragma unroll
-      for (int i = 0; i < K; ++i) { V2n[i] = V2[i]; dV2n[i] = dV2[i]; }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; V2n[i] = 1; dV2n[i] = 0; }
-  }
-  T c0[K], c1[K], c2[K];
-  line_columns<K, D, KA>(Uo, V1, dV1, V2, dV2, c0, c1, c2);
-  T n0[K], n1[K], n2[K];
-  if constexpr (FACE) line_columns<K, D, KA>(Un, V1n, dV1n, V2n, dV2n, n0, n1, n2);
-  T D0[K], D1[K], D2[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) { D0[i] = 0; D1[i] = 0; D2[i] = 0; }
-  // the point data of up to PB points is loaded in one round
-  constexpr int PB = 4;
-  for (int pb = 0; pb < n; pb += PB) {
-    T tk[PB], wq[PB], nvk[PB], nv1[PB], nv2[PB];
+  const bool surf = ((info >> 20) & 0xf) == 1;
+  const T* px = surf ? a.surf_x : a.vol_x;
+  const int64_t stride = surf ? a.n_surf : a.n_vol;
+  const T* pw = surf ? a.surf_w : a.vol_w;
+  const int64_t kbase = surf ? a.seg[4] : a.seg[1];
+  // every global load of the line's first PB points is issued before any
+  // arithmetic
+  const T t1 = px[O1 * stride + p0];
+  const T t2 = D == 3 ? px[O2 * stride + p0] : T(0);
+  T tk[PB], wq[PB], nvk[PB], nv1[PB], nv2[PB];
+  auto load = [&](int pb) {
 #pragma unroll
     for (int i = 0; i < PB; ++i) {
       tk[i] = 0; wq[i] = 0; nvk[i] = 0; nv1[i] = 0; nv2[i] = 0;
       if (pb + i < n) {
         const int64_t q = p0 + pb + i;
-        tk[i] = coord(q, KA);
-        wq[i] = a.hs * pw[q];
+        tk[i] = px[KA * stride + q];
+        wq[i] = pw[q];
         if (a.kappa) wq[i] *= a.kappa[kbase + q];
-        if (kind == 1) {
+        if (surf) {
           nvk[i] = a.surf_n[KA * stride + q];
           nv1[i] = a.surf_n[O1 * stride + q];
           if constexpr (D == 3) nv2[i] = a.surf_n[O2 * stride + q];
         }
       }
     }
+  };
+  load(0);
+  T V1[K], dV1[K], V2[K], dV2[K];
+  lagrange1d<K>(Xn, ID, t1, V1, dV1);
+  if constexpr (D == 3) {
+    lagrange1d<K>(Xn, ID, t2, V2, dV2);
+  } else {
+#pragma unroll
+    for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; }
+  }
+  T c0[K], c1[K], c2[K];
+  line_columns<K, D, KA>(Uo, V1, dV1, V2, dV2, c0, c1, c2);
+  T D0[K], D1[K], D2[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) { D0[i] = 0; D1[i] = 0; D2[i] = 0; }
+  for (int pb = 0; pb < n; pb += PB) {
+    if (pb > 0) load(pb);
 #pragma unroll
     for (int i = 0; i < PB; ++i) {
       if (pb + i >= n) break;
@@ -1102,38 +1083,20 @@ __device__ __forceinline__ void line_work(const T* tab, const DevArgs<T>& a, int
         g1 += Z[ii] * c1[ii];
         g2 += Z[ii] * c2[ii];
       }
-      const T c = wq[i];
+      const T c = a.hs * wq[i];
       T f0, fk, f1, f2;
-      if (kind == 0) {
-        f0 = 0;
-        fk = c * gk;
-        f1 = c * g1;
-        f2 = c * g2;
-      } else if (kind == 1) {
+      if (surf) {
+        // Nitsche: tau u v - d_n u v - u d_n v
         const T dn = nvk[i] * gk + nv1[i] * g1 + nv2[i] * g2;
         f0 = c * (a.tau * val - dn);
         fk = -c * val * nvk[i];
         f1 = -c * val * nv1[i];
         f2 = -c * val * nv2[i];
-      } else if constexpr (FACE) {
-        T vn = 0, gn1 = 0, gn2 = 0;
-#pragma unroll
-        for (int ii = 0; ii < K; ++ii) {
-          vn += Z[ii] * n0[ii];
-          gn1 += Z[ii] * n1[ii];
-          gn2 += Z[ii] * n2[ii];
-        }
-        // the normal derivative is the fixed-axis derivative of that axis
-        const T go = nax == O1 ? g1 : g2;
-        const T gn = nax == O1 ? gn1 : gn2;
-        const T J = sigma * (val - vn);
-        const T A = T(0.5) * (go + gn);
-        f0 = c * sigma * (a.gamma * J - A);
-        fk = 0;
-        f1 = nax == O1 ? T(-0.5) * c * J : T(0);
-        f2 = nax == O1 ? T(0) : T(-0.5) * c * J;
       } else {
-        f0 = fk = f1 = f2 = 0;
+        f0 = 0;
+        fk = c * gk;
+        f1 = c * g1;
+        f2 = c * g2;
       }
 #pragma unroll
       for (int ii = 0; ii < K; ++ii) {
@@ -1143,18 +1106,108 @@ __device__ __forceinline__ void line_work(const T* tab, const DevArgs<T>& a, int
       }
     }
   }
-  rec[0] = T(KA);
+  line_record<K, D>(V1, dV1, V2, dV2, D0, D1, D2, R);
+}
+
+// one cut-face line along cell axis KA, face normal on axis O1 (NSEL = 1) or
+// O2 (NSEL = 2): both traces are evaluated (the normal-axis basis is the
+// tabulated end-point data of either side), SIPG flux, integration against
+// the own cell's test functions.  slot = 2 * normal axis + side.
+template <int K, int D, int KA, int NSEL, typename T>
+__device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a, int info, int p0, int slot,
+                                               const T* Uo, const T* Un, T* R) {
+  constexpr int O1 = KA == 0 ? 1 : 0;
+  constexpr int O2 = KA == 2 ? 1 : 2;
+  constexpr int NAX = NSEL == 1 ? O1 : O2;  // face normal axis
+  constexpr int FAX = NSEL == 1 ? O2 : O1;  // in-face fixed axis (3D)
+  constexpr int PB = 4;
+  const T* Xn = tab + TabOff::X(K);
+  const T* ID = tab + TabOff::ID(K);
+  const int n = info & 0xffff;
+  const int side = slot & 1;
+  const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+  const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+  const T sigma = side ? T(1) : T(-1);
+  const int64_t stride = a.n_fcut;
+  // in-face coordinate index of a cell axis
+  constexpr int FK = KA < NAX ? KA : KA - 1;
+  constexpr int FF = FAX < NAX ? FAX : FAX - 1;
+  const T tf = D == 3 ? a.fcut_x[FF * stride + p0] : T(0);
+  T tk[PB], wq[PB];
+  auto load = [&](int pb) {
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    rec[1 + i] = V1[i];
-    rec[1 + K + i] = dV1[i];
-    rec[1 + 2 * K + i] = D0[i];
-    rec[1 + 3 * K + i] = D1[i];
-    if constexpr (D == 3) {
-      rec[1 + 4 * K + i] = V2[i];
-      rec[1 + 5 * K + i] = dV2[i];
-      rec[1 + 6 * K + i] = D2[i];
+    for (int i = 0; i < PB; ++i) {
+      tk[i] = 0; wq[i] = 0;
+      if (pb + i < n) {
+        const int64_t q = p0 + pb + i;
+        tk[i] = a.fcut_x[FK * stride + q];
+        wq[i] = a.fcut_w[q];
+        if (a.kappa) wq[i] *= a.kappa[a.seg[3] + q];
+      }
     }
+  };
+  load(0);
+  T F[K], dF[K];
+  if constexpr (D == 3) {
+    lagrange1d<K>(Xn, ID, tf, F, dF);
+  } else {
+#pragma unroll
+    for (int i = 0; i < K; ++i) { F[i] = 1; dF[i] = 0; }
+  }
+  T c0[K], c1[K], c2[K], n0[K], n1[K], n2[K];
+  if constexpr (NSEL == 1) {
+    line_columns<K, D, KA>(Uo, Eo, Eo + K, F, dF, c0, c1, c2);
+    line_columns<K, D, KA>(Un, En, En + K, F, dF, n0, n1, n2);
+  } else {
+    line_columns<K, D, KA>(Uo, F, dF, Eo, Eo + K, c0, c1, c2);
+    line_columns<K, D, KA>(Un, F, dF, En, En + K, n0, n1, n2);
+  }
+  T D0[K], Dn[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) { D0[i] = 0; Dn[i] = 0; }
+  for (int pb = 0; pb < n; pb += PB) {
+    if (pb > 0) load(pb);
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      if (pb + i >= n) break;
+      T Z[K], dZ[K];
+      lagrange1d<K>(Xn, ID, tk[i], Z, dZ);
+      T val = 0, go = 0, vn = 0, gn = 0;
+#pragma unroll
+      for (int ii = 0; ii < K; ++ii) {
+        val += Z[ii] * c0[ii];
+        vn += Z[ii] * n0[ii];
+        go += Z[ii] * (NSEL == 1 ? c1[ii] : c2[ii]);
+        gn += Z[ii] * (NSEL == 1 ? n1[ii] : n2[ii]);
+      }
+      // SIPG with the jump sigma (u_own - u_nbr) and the average normal
+      // derivative (the normal derivative is that of the normal axis)
+      const T c = a.hs * wq[i];
+      const T J = sigma * (val - vn);
+      const T A = T(0.5) * (go + gn);
+      const T f0 = c * sigma * (a.gamma * J - A);
+      const T fn = T(-0.5) * c * J;
+#pragma unroll
+      for (int ii = 0; ii < K; ++ii) {
+        D0[ii] += Z[ii] * f0;
+        Dn[ii] += Z[ii] * fn;
+      }
+    }
+  }
+  // record: the normal-axis derivative term carries Dn
+  T zero[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) zero[i] = 0;
+  if constexpr (NSEL == 1) {
+    T e0[K], e1[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) { e0[i] = Eo[i]; e1[i] = Eo[K + i]; }
+    line_record<K, D>(e0, e1, F, dF, D0, Dn, zero, R);
+  } else {
+    T e0[K], e1[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) { e0[i] = Eo[i]; e1[i] = Eo[K + i]; }
+    line_record<K, D>(F, dF, e0, e1, D0, zero, Dn, R);
   }
 }
 
@@ -1162,126 +1215,182 @@ __device__ __forceinline__ void line_work(const T* tab, const DevArgs<T>& a, int
 // one round (or one cell with several rounds); FACE selects the lines of
 // the cut faces (each entry one face of one cell, with the neighbour's DoFs)
 // instead of the volume and interface lines.  The result is added to v.
+// Each lane keeps the sums of its DoFs for every entry of the batch in
+// registers; the records of a round pass through LDS, and as the lines of
+// an entry come ordered by axis, the reduction reads them with fixed index
+// patterns.
 template <int K, int D>
 struct BatchShape {
   static constexpr int ND = ipow(K, D);
-  static constexpr int NT = 64;
-  static constexpr int ME = ND <= 64 ? 16 : 8;  // entries per batch
+  static constexpr int NT = kBatchLines;
+  static constexpr int NPL = (ND + NT - 1) / NT;  // DoFs per lane
   static constexpr int RS = LineShape<K, D>::RS;
+  static constexpr int RP = NT + 1;               // record component pitch
 };
 
 template <int K, int D, typename T, bool FACE>
 struct BatchWork {
-  static constexpr int ND = BatchShape<K, D>::ND, ME = BatchShape<K, D>::ME, NT = BatchShape<K, D>::NT,
-                       RS = BatchShape<K, D>::RS;
+  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), FACE),
+                       RS = BatchShape<K, D>::RS, RP = BatchShape<K, D>::RP;
   T tab[TabOff::size(K)];
   T U[ME][ND];
   T NB[FACE ? ME : 1][FACE ? ND : 1];
-  T OUT[ME][ND];
-  T REC[NT][RS];
+  T REC[RS * RP];  // component c of the round's record r at REC[c * RP + r]
   int ent[ME][4];
-  int rowr[ME];
-  int lofs[ME + 1];
 };
+
+// acc += the records [lo, hi) of the round, all along axis KA
+template <int K, int D, int KA, int NPL, typename T>
+__device__ __forceinline__ void reduce_axis(const T* REC, int lo, int hi, const int (*dof_i)[3], T* acc) {
+  using LS = LineShape<K, D>;
+  constexpr int P = BatchShape<K, D>::RP;
+  constexpr int O1 = KA == 0 ? 1 : 0;
+  constexpr int O2 = KA == 2 ? 1 : 2;
+#pragma unroll 1
+  for (int r = lo; r < hi; ++r) {
+    const T* Rc = REC + r;
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) {
+      const int ik = dof_i[j][KA], i1 = dof_i[j][O1];
+      const T v1 = Rc[(LS::V1 + i1) * P], dv1 = Rc[(LS::DV1 + i1) * P];
+      const T d0 = Rc[(LS::D0 + ik) * P], d1 = Rc[(LS::D1 + ik) * P];
+      if constexpr (D == 3) {
+        const int i2 = dof_i[j][O2];
+        const T v2 = Rc[(LS::V2 + i2) * P], dv2 = Rc[(LS::DV2 + i2) * P], d2 = Rc[(LS::D2 + ik) * P];
+        acc[j] += v2 * (v1 * d0 + dv1 * d1) + v1 * dv2 * d2;
+      } else {
+        acc[j] += v1 * d0 + dv1 * d1;
+      }
+    }
+  }
+}
 
 template <int K, int D, typename T, bool FACE>
 __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                        const int32_t* __restrict__ batches,
-                                                       const int32_t* __restrict__ entries, int n_batches) {
-  constexpr int ND = BatchShape<K, D>::ND, NT = BatchShape<K, D>::NT;
-  __shared__ BatchWork<K, D, T, FACE> W;
-  for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
+                                                       const int32_t* __restrict__ entries,
+                                                       const int32_t* __restrict__ lines, int n_batches) {
+  using BW = BatchWork<K, D, T, FACE>;
+  constexpr int ND = BW::ND, ME = BW::ME, RS = BW::RS, RP = BW::RP, NT = BatchShape<K, D>::NT,
+                NPL = BatchShape<K, D>::NPL;
+  constexpr int OFS = (1 << kBatchOffsetBits) - 1;
+  __shared__ BW W;
   const int t = threadIdx.x;
+  for (int i = t; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   const bool do_vol = (a.terms & 1) != 0, do_surf = (a.terms & 4) != 0;
+  // tensor index of the lane's DoFs
+  int dof_i[NPL][3];
+#pragma unroll
+  for (int j = 0; j < NPL; ++j) {
+    const int l = min(t + NT * j, ND - 1);
+    dof_i[j][0] = l % K;
+    dof_i[j][1] = (l / K) % K;
+    dof_i[j][2] = D == 3 ? l / (K * K) : 0;
+  }
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
-    const int e0 = batches[2 * b], ne = batches[2 * b + 1];
-    if (t < 4 * ne) W.ent[t / 4][t % 4] = entries[4 * (e0 + t / 4) + t % 4];
+    const int e0 = batches[4 * b], ne = batches[4 * b + 1], total = batches[4 * b + 2], l0 = batches[4 * b + 3];
+    if (t < 4 * ne) (&W.ent[0][0])[t] = entries[4 * e0 + t];
+    // descriptor of the lane's line in the first round
+    int2 hd = make_int2(0, 0);
+    if (t < total) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + t));
     sync();
-    if (t < ne) {
-      const int r = a.cut_rank[W.ent[t][0]];
-      W.rowr[t] = r;
+    int rank[ME], ofs[ME + 1], n0[ME], n1[ME];
+#pragma unroll
+    for (int e = 0; e < ME; ++e) {
+      rank[e] = e < ne ? W.ent[e][0] : -1;
+      ofs[e] = e < ne ? (W.ent[e][2] & OFS) : total;
+      n0[e] = W.ent[e][1] & 0xffff;
+      n1[e] = (W.ent[e][1] >> 16) & 0xffff;
     }
-    if (t == 0) {
-      int acc = 0;
-      for (int e = 0; e < ne; ++e) {
-        W.lofs[e] = acc;
-        acc += W.ent[e][2] - W.ent[e][1];
-      }
-      W.lofs[ne] = acc;
-    }
-    sync();
+    ofs[ME] = total;
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
-      W.U[e][l] = x[(int64_t)W.rowr[e] * ND + l];
-      if constexpr (FACE) {
-        const int nbr = a.nb[(int64_t)W.rowr[e] * 2 * D + W.ent[e][3]];
-        W.NB[e][l] = x[(int64_t)nbr * ND + l];
+      W.U[e][l] = x[(int64_t)W.ent[e][0] * ND + l];
+      if constexpr (FACE) W.NB[e][l] = x[(int64_t)W.ent[e][3] * ND + l];
+    }
+    // per-entry sums of the lane's DoFs; the first entry of a cell starts
+    // from the row of v
+    T acc[ME][NPL];
+#pragma unroll
+    for (int e = 0; e < ME; ++e) {
+      const bool first = e < ne && (e == 0 || rank[e - 1] != rank[e]);
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        const int l = t + NT * j;
+        acc[e][j] = (first && l < ND) ? v[(int64_t)rank[e] * ND + l] : T(0);
       }
-      W.OUT[e][l] = 0;
     }
     sync();
-    const int total = W.lofs[ne];
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
-      T* rec = W.REC[t];
+      T R[RS];
+#pragma unroll
+      for (int c = 0; c < RS; ++c) R[c] = 0;
       if (g < total) {
-        int e = 0;
-        while (g >= W.lofs[e + 1]) ++e;
-        const int lid = W.ent[e][1] + (g - W.lofs[e]);
-        const int info = a.line_info[lid];
+        if (base > 0) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + g));
+        const int info = hd.y & 0xffffff, e = hd.y >> 24;
+        const int slot = W.ent[e][2] >> kBatchOffsetBits;
         const int kind = (info >> 20) & 0xf;
         const bool on = FACE || (kind == 0 ? do_vol : do_surf);
         int ax = (info >> 16) & 0xf;
-        const int s = FACE ? W.ent[e][3] : -1;
+        const T* Uo = &W.U[0][0] + e * ND;
         if constexpr (FACE) {
-          const int nax = s >> 1;
+          const int nax = slot >> 1;
           ax = ax < nax ? ax : ax + 1;
-        }
-        const T* Un = FACE ? &W.NB[e][0] : nullptr;
-        if (!on) {
-          rec[0] = T(0);
-          for (int i = 1; i < BatchShape<K, D>::RS; ++i) rec[i] = T(0);
-        } else if (ax == 0) line_work<K, D, 0, FACE>(W.tab, a, lid, s, W.U[e], Un, rec);
-        else if (ax == 1 || D == 2) line_work<K, D, 1, FACE>(W.tab, a, lid, s, W.U[e], Un, rec);
-        else if constexpr (D == 3) line_work<K, D, 2, FACE>(W.tab, a, lid, s, W.U[e], Un, rec);
-      }
-      sync();
-      // records of this round, entry by entry
-      for (int e = 0; e < ne; ++e) {
-        const int r0 = max(W.lofs[e], base) - base, r1 = min(W.lofs[e + 1], base + NT) - base;
-        if (r1 <= r0) continue;
-        for (int l = t; l < ND; l += NT) {
-          const int c[3] = {l % K, (l / K) % K, D == 3 ? l / (K * K) : 0};
-          T sum = 0;
-          for (int rr = r0; rr < r1; ++rr) {
-            const T* R2 = W.REC[rr];
-            const int ka = (int)R2[0];
-            const int o1 = ka == 0 ? 1 : 0, o2 = ka == 2 ? 1 : 2;
-            const int lk = c[ka], l1 = c[o1];
-            if constexpr (D == 3) {
-              const int l2 = c[o2];
-              const T v2 = R2[1 + 4 * K + l2];
-              sum += v2 * (R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk]) +
-                     R2[1 + l1] * R2[1 + 5 * K + l2] * R2[1 + 6 * K + lk];
+          const T* Un = &W.NB[0][0] + e * ND;
+          // normal axis: the lower (NSEL 1) or upper (NSEL 2) fixed axis
+          const bool lower = nax == (ax == 0 ? 1 : 0);
+          if constexpr (D == 2) {
+            if (ax == 0) line_work_face<K, D, 0, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
+            else line_work_face<K, D, 1, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
+          } else {
+            if (ax == 0) {
+              if (lower) line_work_face<K, D, 0, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
+              else line_work_face<K, D, 0, 2>(W.tab, a, info, hd.x, slot, Uo, Un, R);
+            } else if (ax == 1) {
+              if (lower) line_work_face<K, D, 1, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
+              else line_work_face<K, D, 1, 2>(W.tab, a, info, hd.x, slot, Uo, Un, R);
             } else {
-              sum += R2[1 + l1] * R2[1 + 2 * K + lk] + R2[1 + K + l1] * R2[1 + 3 * K + lk];
+              if (lower) line_work_face<K, D, 2, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
+              else line_work_face<K, D, 2, 2>(W.tab, a, info, hd.x, slot, Uo, Un, R);
             }
           }
-          W.OUT[e][l] += sum;
+        } else if (on) {
+          if (ax == 0) line_work_cell<K, D, 0>(W.tab, a, info, hd.x, Uo, R);
+          else if (ax == 1 || D == 2) line_work_cell<K, D, 1>(W.tab, a, info, hd.x, Uo, R);
+          else if constexpr (D == 3) line_work_cell<K, D, 2>(W.tab, a, info, hd.x, Uo, R);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = R[c];
+      sync();
+      const int r1 = min(total, base + NT);
+#pragma unroll
+      for (int e = 0; e < ME; ++e) {
+        if (e < ne && ofs[e] < r1 && ofs[e + 1] > base) {
+          const int a0 = ofs[e], a1 = a0 + n0[e], a2 = a1 + n1[e], a3 = ofs[e + 1];
+          reduce_axis<K, D, 0, NPL>(W.REC, max(a0, base) - base, min(a1, r1) - base, dof_i, acc[e]);
+          reduce_axis<K, D, 1, NPL>(W.REC, max(a1, base) - base, min(a2, r1) - base, dof_i, acc[e]);
+          if constexpr (D == 3) reduce_axis<K, D, 2, NPL>(W.REC, max(a2, base) - base, min(a3, r1) - base, dof_i, acc[e]);
         }
       }
       sync();
     }
-    // entries of one cell are consecutive: add their sum once
-    for (int idx = t; idx < ne * ND; idx += NT) {
-      const int e = idx / ND, l = idx % ND;
-      if (e > 0 && W.rowr[e - 1] == W.rowr[e]) continue;
-      T sum = W.OUT[e][l];
-      for (int e2 = e + 1; e2 < ne && W.rowr[e2] == W.rowr[e]; ++e2) sum += W.OUT[e2][l];
-      T* out = v + (int64_t)W.rowr[e] * ND + l;
-      *out += sum;
+    // entries of one cell are consecutive: their sums go out once
+#pragma unroll
+    for (int e = 0; e < ME; ++e) {
+      if (e < ne && (e == 0 || rank[e - 1] != rank[e])) {
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          T s = acc[e][j];
+#pragma unroll
+          for (int e2 = e + 1; e2 < ME; ++e2)
+            if (e2 < ne && rank[e2] == rank[e]) s += acc[e2][j];
+          const int l = t + NT * j;
+          if (l < ND) v[(int64_t)rank[e] * ND + l] = s;
+        }
+      }
     }
-    sync();
   }
 }
 
@@ -1466,16 +1575,14 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
 // cut cells: the point lines of the volume / interface (FACE = false) or of
 // the cut faces (FACE = true), with both arguments evaluated at every point
 template <int K, int D, int KA, bool FACE, typename T>
-__device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int lid, int slot, const T* Wo, const T* Wn,
-                                        const T* Yo, const T* Yn, T* __restrict__ dk) {
+__device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int info, int p0, int slot, const T* Wo,
+                                        const T* Wn, const T* Yo, const T* Yn, T* __restrict__ dk) {
   constexpr int O1 = KA == 0 ? 1 : 0;
   constexpr int O2 = KA == 2 ? 1 : 2;
   const T* Xn = tab + TabOff::X(K);
   const T* ID = tab + TabOff::ID(K);
-  const int info = a.line_info[lid];
   const int n = info & 0xffff;
   const int kind = FACE ? 2 : ((info >> 20) & 0xf);
-  const int p0 = a.line_first[lid];
   const T* px;
   int64_t stride, kbase;
   const T* pw;
@@ -1590,67 +1697,55 @@ __device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int l
 
 template <int K, int D, typename T, bool FACE>
 struct DkBatchWork {
-  static constexpr int ND = BatchShape<K, D>::ND, ME = BatchShape<K, D>::ME;
+  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), FACE);
   T tab[TabOff::size(K)];
   T Wo[ME][ND];
   T Yo[ME][ND];
   T Wn[FACE ? ME : 1][FACE ? ND : 1];
   T Yn[FACE ? ME : 1][FACE ? ND : 1];
   int ent[ME][4];
-  int rowr[ME];
-  int lofs[ME + 1];
 };
 
 template <int K, int D, typename T, bool FACE>
 __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __restrict__ w, const T* __restrict__ u,
                                                     T* __restrict__ dk, const int32_t* __restrict__ batches,
-                                                    const int32_t* __restrict__ entries, int n_batches) {
-  constexpr int ND = BatchShape<K, D>::ND, NT = 64;
-  __shared__ DkBatchWork<K, D, T, FACE> W;
+                                                    const int32_t* __restrict__ entries,
+                                                    const int32_t* __restrict__ lines, int n_batches) {
+  using BW = DkBatchWork<K, D, T, FACE>;
+  constexpr int ND = BW::ND, ME = BW::ME, NT = 64;
+  __shared__ BW W;
   for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   const int t = threadIdx.x;
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
-    const int e0 = batches[2 * b], ne = batches[2 * b + 1];
-    if (t < 4 * ne) W.ent[t / 4][t % 4] = entries[4 * (e0 + t / 4) + t % 4];
-    sync();
-    if (t < ne) W.rowr[t] = a.cut_rank[W.ent[t][0]];
-    if (t == 0) {
-      int acc = 0;
-      for (int e = 0; e < ne; ++e) {
-        W.lofs[e] = acc;
-        acc += W.ent[e][2] - W.ent[e][1];
-      }
-      W.lofs[ne] = acc;
-    }
+    const int e0 = batches[4 * b], ne = batches[4 * b + 1], total = batches[4 * b + 2], l0 = batches[4 * b + 3];
+    if (t < 4 * ne) (&W.ent[0][0])[t] = entries[4 * e0 + t];
     sync();
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
-      const int64_t ro = (int64_t)W.rowr[e] * ND + l;
+      const int64_t ro = (int64_t)W.ent[e][0] * ND + l;
       W.Wo[e][l] = w[ro];
       W.Yo[e][l] = u[ro];
       if constexpr (FACE) {
-        const int64_t rn = (int64_t)a.nb[(int64_t)W.rowr[e] * 2 * D + W.ent[e][3]] * ND + l;
+        const int64_t rn = (int64_t)W.ent[e][3] * ND + l;
         W.Wn[e][l] = w[rn];
         W.Yn[e][l] = u[rn];
       }
     }
     sync();
-    const int total = W.lofs[ne];
     for (int g = t; g < total; g += NT) {
-      int e = 0;
-      while (g >= W.lofs[e + 1]) ++e;
-      const int lid = W.ent[e][1] + (g - W.lofs[e]);
-      int ax = (a.line_info[lid] >> 16) & 0xf;
-      const int s = FACE ? W.ent[e][3] : -1;
+      const int2 hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + g));
+      const int info = hd.y & 0xffffff, e = hd.y >> 24;
+      int ax = (info >> 16) & 0xf;
+      const int s = W.ent[e][2] >> kBatchOffsetBits;
       if constexpr (FACE) {
         const int nax = s >> 1;
         ax = ax < nax ? ax : ax + 1;
       }
       const T* Wn = FACE ? &W.Wn[e][0] : nullptr;
       const T* Yn = FACE ? &W.Yn[e][0] : nullptr;
-      if (ax == 0) line_dk<K, D, 0, FACE>(W.tab, a, lid, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
-      else if (ax == 1 || D == 2) line_dk<K, D, 1, FACE>(W.tab, a, lid, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
-      else if constexpr (D == 3) line_dk<K, D, 2, FACE>(W.tab, a, lid, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
+      if (ax == 0) line_dk<K, D, 0, FACE>(W.tab, a, info, hd.x, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
+      else if (ax == 1 || D == 2) line_dk<K, D, 1, FACE>(W.tab, a, info, hd.x, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
+      else if constexpr (D == 3) line_dk<K, D, 2, FACE>(W.tab, a, info, hd.x, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
     }
     sync();
   }
@@ -1665,7 +1760,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     // A is symmetric: A^T w is the fast apply of w; dkappa from the
     // evaluation kernels
     DevArgs<T> b = a;
-    b.parts = 3;
+    b.parts = 15;
     hipError_t e = launch_kd<K, D, T>(b, x, nullptr, v, nullptr, false, s);
     if (e != hipSuccess || dk == nullptr) return e;
     if constexpr (ipow(K, D) <= 125) {
@@ -1676,10 +1771,10 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
         face_dk_kernel<K, D, T><<<(int)std::min<int64_t>((a.n_sfaces + CF - 1) / CF, 1 << 20), 64, 0, s>>>(a, x, y, dk);
       if (a.n_vbatch > 0)
         cut_dk_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.vbatch, a.ventry,
-                                                                                   a.n_vbatch);
+                                                                                   a.vline, a.n_vbatch);
       if (a.n_fbatch > 0)
         cut_dk_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.fbatch, a.fentry,
-                                                                                  a.n_fbatch);
+                                                                                  a.fline, a.n_fbatch);
     }
     return hipGetLastError();
   }
@@ -1700,15 +1795,13 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
         // lines are added
         constexpr int CW = KronShape<K, D>::C;
         const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
-        if (gs > 0) {
-          inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
-          if ((a.terms & 5) && a.n_vbatch > 0)
-            cut_batch_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.vbatch, a.ventry,
-                                                                                          a.n_vbatch);
-          if ((a.terms & 2) && a.n_fbatch > 0)
-            cut_batch_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.fbatch, a.fentry,
-                                                                                         a.n_fbatch);
-        }
+        if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
+        if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0)
+          cut_batch_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.vbatch, a.ventry,
+                                                                                        a.vline, a.n_vbatch);
+        if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0)
+          cut_batch_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.fbatch, a.fentry,
+                                                                                       a.fline, a.n_fbatch);
       }
     } else {
       if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);

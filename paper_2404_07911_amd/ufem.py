@@ -199,7 +199,13 @@ class Operator:
         return v
 
     def apply_part(self, part, u, v, stream=None):
-        """One kernel of the apply (1: inside cells, 2: cut cells)."""
+        """Kernel stages of the apply (mask of PART_* bits: 1 inside cells,
+        2 cut cells' structured faces, 4 cut volume/interface lines, 8 cut-face
+        lines; 4 and 8 add to v)."""
+        self._check_vec(u, self.n_dofs, "u")
+        self._check_vec(v, self.n_dofs, "v")
+        if v.dtype != u.dtype:
+            raise TypeError("u and v must share a dtype")
         L.check(L.lib().ufem_apply_part(self._h, _prec_of(u), int(part), C.c_void_p(u.data_ptr()),
                                         C.c_void_p(v.data_ptr()), _stream_handle(stream)))
         return v

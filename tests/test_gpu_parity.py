@@ -113,6 +113,36 @@ def test_adjoint_and_dkappa_constant_kappa(torch, name):
     assert _rel(dk32.cpu().numpy().astype(np.float64), ora.dkappa(w64, u64)) < TOL32
 
 
+@pytest.mark.parametrize("name", ["ball3d_p3", "disk2d_p2", "balls3d_p2"])
+def test_apply_stages_compose(torch, name):
+    """The kernel stages, one call each, give ufem_apply bit for bit, on the
+    kappa = 1 path (structured faces, then volume/interface and cut-face
+    lines) and on the quadrature path of a kappa field."""
+    from paper_2404_07911_amd import PART_CUT, PART_INSIDE, UfemError
+
+    wl, ora, pl, op, u, w = _setup(name)
+    ud = torch.from_numpy(u).cuda()
+    kap = torch.from_numpy(ui.kappa_field(ora.qp_physical_points())).cuda()
+    try:
+        for k in (None, kap):
+            _say(f"[{name}] stages, kappa {'field' if k is not None else '1'}")
+            op.set_kappa(k)
+            full = op.apply(ud)
+            v = torch.full_like(ud, float("nan"))
+            for part in (1, 2, 4, 8):
+                op.apply_part(part, ud, v)
+            assert torch.equal(v, full)
+            v = torch.full_like(ud, float("nan"))
+            op.apply_part(PART_INSIDE, ud, v)
+            op.apply_part(PART_CUT, ud, v)
+            assert torch.equal(v, full)
+        for bad in (0, 16, -1):
+            with pytest.raises(UfemError):
+                op.apply_part(bad, ud, v)
+    finally:
+        op.set_kappa(None)
+
+
 def test_apply_is_repeatable_and_overwrites(torch):
     wl, ora, pl, op, u, w = _setup("ball3d_p3")
     ud = torch.from_numpy(u).cuda()
