@@ -486,19 +486,20 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         int nl = 0, n_e = (int)ce.size() / 4;
         for (int e = 0; e < n_e; ++e) nl += ce[4 * e + 1] - ce[4 * e];
         if (cur_n > 0 && (cur_lines + nl > ufem::kBatchLines || cur_n + n_e > me)) close();
-        if (n_e > me || cur_lines + nl >= (1 << ufem::kBatchOffsetBits)) {
+        for (int e = 0; e < n_e; ++e)
+          if (face && ce[4 * e + 3] < 0) batch_overflow = true;  // a cut face always has a neighbour
+        if (batch_overflow || n_e > me || cur_lines + nl >= (1 << ufem::kBatchOffsetBits)) {
           batch_overflow = true;
           return;
         }
         for (int e = 0; e < n_e; ++e) {
           const int32_t lb = ce[4 * e], le = ce[4 * e + 1], sl = ce[4 * e + 2];
-          const int nax = sl >> 1;
+          // volume lines by cell axis, face lines by in-face axis (the same
+          // order, the in-face axes being the other cell axes ascending)
           int cnt[3] = {0, 0, 0};
           for (int ax = 0; ax < P.dim; ++ax)
             for (int32_t l = lb; l < le; ++l) {
-              int la = P.line_axis[l];
-              if (face) la = la < nax ? la : la + 1;  // in-face axis -> cell axis
-              if (la != ax) continue;
+              if (P.line_axis[l] != ax) continue;
               blines.push_back((int32_t)P.line_first[l]);
               blines.push_back(linfo[l] | ((cur_n + e) << 24));
               ++cnt[ax];

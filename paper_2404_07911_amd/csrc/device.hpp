@@ -30,9 +30,11 @@ constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
 // along axis 0 | lines along axis 1 << 16, offset of the entry's first line
 // in the batch | slot << 24, active rank of the neighbour across the slot or
 // -1).  Line descriptor = (first point, count | axis << 16 | kind << 20 |
-// entry << 24); the lines of an entry are consecutive and ordered by cell
-// axis.  Entries of one cell are consecutive and in one batch.
-constexpr __host__ __device__ int batch_max_entries(int, bool) { return 8; }
+// entry << 24); the lines of an entry are consecutive and ordered by axis.
+// Axes are cell axes for volume / interface entries (slot 15) and in-face
+// axes for cut-face entries (one per cut face of a cut cell).  Entries of one
+// cell are consecutive and in one batch.
+constexpr __host__ __device__ int batch_max_entries(int, bool face) { return face ? 12 : 8; }
 constexpr int kBatchLines = 64;        // lines per round (one per lane)
 constexpr int kBatchOffsetBits = 24;   // bits of the in-batch line offset
 

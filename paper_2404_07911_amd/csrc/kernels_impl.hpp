@@ -1109,112 +1109,8 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
   line_record<K, D>(V1, dV1, V2, dV2, D0, D1, D2, R);
 }
 
-// one cut-face line along cell axis KA, face normal on axis O1 (NSEL = 1) or
-// O2 (NSEL = 2): both traces are evaluated (the normal-axis basis is the
-// tabulated end-point data of either side), SIPG flux, integration against
-// the own cell's test functions.  slot = 2 * normal axis + side.
-template <int K, int D, int KA, int NSEL, typename T>
-__device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a, int info, int p0, int slot,
-                                               const T* Uo, const T* Un, T* R) {
-  constexpr int O1 = KA == 0 ? 1 : 0;
-  constexpr int O2 = KA == 2 ? 1 : 2;
-  constexpr int NAX = NSEL == 1 ? O1 : O2;  // face normal axis
-  constexpr int FAX = NSEL == 1 ? O2 : O1;  // in-face fixed axis (3D)
-  constexpr int PB = 4;
-  const T* Xn = tab + TabOff::X(K);
-  const T* ID = tab + TabOff::ID(K);
-  const int n = info & 0xffff;
-  const int side = slot & 1;
-  const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-  const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-  const T sigma = side ? T(1) : T(-1);
-  const int64_t stride = a.n_fcut;
-  // in-face coordinate index of a cell axis
-  constexpr int FK = KA < NAX ? KA : KA - 1;
-  constexpr int FF = FAX < NAX ? FAX : FAX - 1;
-  const T tf = D == 3 ? a.fcut_x[FF * stride + p0] : T(0);
-  T tk[PB], wq[PB];
-  auto load = [&](int pb) {
-#pragma unroll
-    for (int i = 0; i < PB; ++i) {
-      tk[i] = 0; wq[i] = 0;
-      if (pb + i < n) {
-        const int64_t q = p0 + pb + i;
-        tk[i] = a.fcut_x[FK * stride + q];
-        wq[i] = a.fcut_w[q];
-        if (a.kappa) wq[i] *= a.kappa[a.seg[3] + q];
-      }
-    }
-  };
-  load(0);
-  T F[K], dF[K];
-  if constexpr (D == 3) {
-    lagrange1d<K>(Xn, ID, tf, F, dF);
-  } else {
-#pragma unroll
-    for (int i = 0; i < K; ++i) { F[i] = 1; dF[i] = 0; }
-  }
-  T c0[K], c1[K], c2[K], n0[K], n1[K], n2[K];
-  if constexpr (NSEL == 1) {
-    line_columns<K, D, KA>(Uo, Eo, Eo + K, F, dF, c0, c1, c2);
-    line_columns<K, D, KA>(Un, En, En + K, F, dF, n0, n1, n2);
-  } else {
-    line_columns<K, D, KA>(Uo, F, dF, Eo, Eo + K, c0, c1, c2);
-    line_columns<K, D, KA>(Un, F, dF, En, En + K, n0, n1, n2);
-  }
-  T D0[K], Dn[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) { D0[i] = 0; Dn[i] = 0; }
-  for (int pb = 0; pb < n; pb += PB) {
-    if (pb > 0) load(pb);
-#pragma unroll
-    for (int i = 0; i < PB; ++i) {
-      if (pb + i >= n) break;
-      T Z[K], dZ[K];
-      lagrange1d<K>(Xn, ID, tk[i], Z, dZ);
-      T val = 0, go = 0, vn = 0, gn = 0;
-#pragma unroll
-      for (int ii = 0; ii < K; ++ii) {
-        val += Z[ii] * c0[ii];
-        vn += Z[ii] * n0[ii];
-        go += Z[ii] * (NSEL == 1 ? c1[ii] : c2[ii]);
-        gn += Z[ii] * (NSEL == 1 ? n1[ii] : n2[ii]);
-      }
-      // SIPG with the jump sigma (u_own - u_nbr) and the average normal
-      // derivative (the normal derivative is that of the normal axis)
-      const T c = a.hs * wq[i];
-      const T J = sigma * (val - vn);
-      const T A = T(0.5) * (go + gn);
-      const T f0 = c * sigma * (a.gamma * J - A);
-      const T fn = T(-0.5) * c * J;
-#pragma unroll
-      for (int ii = 0; ii < K; ++ii) {
-        D0[ii] += Z[ii] * f0;
-        Dn[ii] += Z[ii] * fn;
-      }
-    }
-  }
-  // record: the normal-axis derivative term carries Dn
-  T zero[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) zero[i] = 0;
-  if constexpr (NSEL == 1) {
-    T e0[K], e1[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) { e0[i] = Eo[i]; e1[i] = Eo[K + i]; }
-    line_record<K, D>(e0, e1, F, dF, D0, Dn, zero, R);
-  } else {
-    T e0[K], e1[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) { e0[i] = Eo[i]; e1[i] = Eo[K + i]; }
-    line_record<K, D>(F, dF, e0, e1, D0, zero, Dn, R);
-  }
-}
-
 // Batched line kernels: one wave per batch of cut cells whose lines fit in
-// one round (or one cell with several rounds); FACE selects the lines of
-// the cut faces (each entry one face of one cell, with the neighbour's DoFs)
-// instead of the volume and interface lines.  The result is added to v.
+// one round (or one cell with several rounds).  The result is added to v.
 // Each lane keeps the sums of its DoFs for every entry of the batch in
 // registers; the records of a round pass through LDS, and as the lines of
 // an entry come ordered by axis, the reduction reads them with fixed index
@@ -1224,17 +1120,63 @@ struct BatchShape {
   static constexpr int ND = ipow(K, D);
   static constexpr int NT = kBatchLines;
   static constexpr int NPL = (ND + NT - 1) / NT;  // DoFs per lane
-  static constexpr int RS = LineShape<K, D>::RS;
   static constexpr int RP = NT + 1;               // record component pitch
 };
 
-template <int K, int D, typename T, bool FACE>
+// tensor index of the lane's DoFs
+template <int K, int D, int NPL>
+__device__ __forceinline__ void lane_dofs(int (*dof_i)[3]) {
+#pragma unroll
+  for (int j = 0; j < NPL; ++j) {
+    const int l = min((int)threadIdx.x + kBatchLines * j, ipow(K, D) - 1);
+    dof_i[j][0] = l % K;
+    dof_i[j][1] = (l / K) % K;
+    dof_i[j][2] = D == 3 ? l / (K * K) : 0;
+  }
+}
+
+// the batch's entries: sums of the lane's DoFs start from v's row for the
+// first entry of a cell; at the end the entries of a cell go out once
+template <int K, int D, int ME, int NPL, typename T>
+__device__ __forceinline__ void batch_acc_init(const T* __restrict__ v, const int* rank, int ne, T (*acc)[NPL]) {
+  constexpr int ND = ipow(K, D);
+#pragma unroll
+  for (int e = 0; e < ME; ++e) {
+    const bool first = e < ne && (e == 0 || rank[e - 1] != rank[e]);
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) {
+      const int l = threadIdx.x + kBatchLines * j;
+      acc[e][j] = (first && l < ND) ? v[(int64_t)rank[e] * ND + l] : T(0);
+    }
+  }
+}
+
+template <int K, int D, int ME, int NPL, typename T>
+__device__ __forceinline__ void batch_acc_store(T* __restrict__ v, const int* rank, int ne, T (*acc)[NPL]) {
+  constexpr int ND = ipow(K, D);
+#pragma unroll
+  for (int e = 0; e < ME; ++e) {
+    if (e < ne && (e == 0 || rank[e - 1] != rank[e])) {
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        T s = acc[e][j];
+#pragma unroll
+        for (int e2 = e + 1; e2 < ME; ++e2)
+          if (e2 < ne && rank[e2] == rank[e]) s += acc[e2][j];
+        const int l = threadIdx.x + kBatchLines * j;
+        if (l < ND) v[(int64_t)rank[e] * ND + l] = s;
+      }
+    }
+  }
+}
+
+// ---- volume and interface lines
+template <int K, int D, typename T>
 struct BatchWork {
-  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), FACE),
-                       RS = BatchShape<K, D>::RS, RP = BatchShape<K, D>::RP;
+  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false),
+                       RS = LineShape<K, D>::RS, RP = BatchShape<K, D>::RP;
   T tab[TabOff::size(K)];
   T U[ME][ND];
-  T NB[FACE ? ME : 1][FACE ? ND : 1];
   T REC[RS * RP];  // component c of the round's record r at REC[c * RP + r]
   int ent[ME][4];
 };
@@ -1265,12 +1207,12 @@ __device__ __forceinline__ void reduce_axis(const T* REC, int lo, int hi, const 
   }
 }
 
-template <int K, int D, typename T, bool FACE>
+template <int K, int D, typename T>
 __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                        const int32_t* __restrict__ batches,
                                                        const int32_t* __restrict__ entries,
                                                        const int32_t* __restrict__ lines, int n_batches) {
-  using BW = BatchWork<K, D, T, FACE>;
+  using BW = BatchWork<K, D, T>;
   constexpr int ND = BW::ND, ME = BW::ME, RS = BW::RS, RP = BW::RP, NT = BatchShape<K, D>::NT,
                 NPL = BatchShape<K, D>::NPL;
   constexpr int OFS = (1 << kBatchOffsetBits) - 1;
@@ -1278,15 +1220,8 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
   const int t = threadIdx.x;
   for (int i = t; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   const bool do_vol = (a.terms & 1) != 0, do_surf = (a.terms & 4) != 0;
-  // tensor index of the lane's DoFs
   int dof_i[NPL][3];
-#pragma unroll
-  for (int j = 0; j < NPL; ++j) {
-    const int l = min(t + NT * j, ND - 1);
-    dof_i[j][0] = l % K;
-    dof_i[j][1] = (l / K) % K;
-    dof_i[j][2] = D == 3 ? l / (K * K) : 0;
-  }
+  lane_dofs<K, D, NPL>(dof_i);
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     const int e0 = batches[4 * b], ne = batches[4 * b + 1], total = batches[4 * b + 2], l0 = batches[4 * b + 3];
     if (t < 4 * ne) (&W.ent[0][0])[t] = entries[4 * e0 + t];
@@ -1306,20 +1241,9 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
       W.U[e][l] = x[(int64_t)W.ent[e][0] * ND + l];
-      if constexpr (FACE) W.NB[e][l] = x[(int64_t)W.ent[e][3] * ND + l];
     }
-    // per-entry sums of the lane's DoFs; the first entry of a cell starts
-    // from the row of v
     T acc[ME][NPL];
-#pragma unroll
-    for (int e = 0; e < ME; ++e) {
-      const bool first = e < ne && (e == 0 || rank[e - 1] != rank[e]);
-#pragma unroll
-      for (int j = 0; j < NPL; ++j) {
-        const int l = t + NT * j;
-        acc[e][j] = (first && l < ND) ? v[(int64_t)rank[e] * ND + l] : T(0);
-      }
-    }
+    batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
     sync();
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
@@ -1329,33 +1253,10 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
       if (g < total) {
         if (base > 0) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + g));
         const int info = hd.y & 0xffffff, e = hd.y >> 24;
-        const int slot = W.ent[e][2] >> kBatchOffsetBits;
         const int kind = (info >> 20) & 0xf;
-        const bool on = FACE || (kind == 0 ? do_vol : do_surf);
-        int ax = (info >> 16) & 0xf;
+        const int ax = (info >> 16) & 0xf;
         const T* Uo = &W.U[0][0] + e * ND;
-        if constexpr (FACE) {
-          const int nax = slot >> 1;
-          ax = ax < nax ? ax : ax + 1;
-          const T* Un = &W.NB[0][0] + e * ND;
-          // normal axis: the lower (NSEL 1) or upper (NSEL 2) fixed axis
-          const bool lower = nax == (ax == 0 ? 1 : 0);
-          if constexpr (D == 2) {
-            if (ax == 0) line_work_face<K, D, 0, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-            else line_work_face<K, D, 1, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-          } else {
-            if (ax == 0) {
-              if (lower) line_work_face<K, D, 0, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-              else line_work_face<K, D, 0, 2>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-            } else if (ax == 1) {
-              if (lower) line_work_face<K, D, 1, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-              else line_work_face<K, D, 1, 2>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-            } else {
-              if (lower) line_work_face<K, D, 2, 1>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-              else line_work_face<K, D, 2, 2>(W.tab, a, info, hd.x, slot, Uo, Un, R);
-            }
-          }
-        } else if (on) {
+        if (kind == 0 ? do_vol : do_surf) {
           if (ax == 0) line_work_cell<K, D, 0>(W.tab, a, info, hd.x, Uo, R);
           else if (ax == 1 || D == 2) line_work_cell<K, D, 1>(W.tab, a, info, hd.x, Uo, R);
           else if constexpr (D == 3) line_work_cell<K, D, 2>(W.tab, a, info, hd.x, Uo, R);
@@ -1376,21 +1277,244 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
       }
       sync();
     }
-    // entries of one cell are consecutive: their sums go out once
+    batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
+  }
+}
+
+// ---- cut-face lines
+// Each entry is one cut face of a cut cell (slot s = 2 N + side, N the
+// normal axis).  The DoFs of the cell and of the neighbour across the face
+// are staged transposed to (normal axis, in-face axis A, in-face axis B),
+// A < B the other cell axes, so that one code path serves lines along A and
+// along B: the columns along the line contract the normal axis with the
+// tabulated end-point values (and first derivatives) of either side and the
+// other in-face axis with the Lagrange values of the line's coordinate.
+// The SIPG flux needs the value and the normal derivative of both traces
+// only, and the line record is [VF | D0 | DN] (3D) or [D0 | DN] (2D): the
+// test-function coefficient of DoF (i_line, i_N, i_F) is
+// VF[i_F] (E[i_N] D0[i_line] + E'[i_N] DN[i_line]) with E the own side's
+// end-point values.
+template <int K, int D>
+struct FaceShape {
+  static constexpr int NF = ipow(K, D - 1);
+  static constexpr int RS = D == 3 ? 3 * K : 2 * K;
+  static constexpr int VF = 0, D0 = D == 3 ? K : 0, DN = D0 + K;
+};
+
+template <int K, int D, typename T>
+struct FaceWork {
+  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), true),
+                       RS = FaceShape<K, D>::RS, RP = BatchShape<K, D>::RP;
+  T tab[TabOff::size(K)];
+  T U[ME][ND];   // transposed: U[e][iN * K^(D-1) + iA * K^(D-2) + iB]
+  T NB[ME][ND];
+  T REC[RS * RP];
+  int ent[ME][4];
+};
+
+// one cut-face line, along in-face axis A (alongB false) or B
+template <int K, int D, typename T>
+__device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a, int info, int p0, int slot,
+                                               bool alongB, const T* Uo, const T* Un, T* R) {
+  using FS = FaceShape<K, D>;
+  constexpr int PB = 4;
+  constexpr int NF = FS::NF;
+  const T* Xn = tab + TabOff::X(K);
+  const T* ID = tab + TabOff::ID(K);
+  const int n = info & 0xffff;
+  const int side = slot & 1;
+  const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+  const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+  const T sigma = side ? T(1) : T(-1);
+  const int64_t stride = a.n_fcut;
+  // in-face coordinates: index 0 along A, 1 along B
+  const int fk = alongB ? 1 : 0;
+  const T tf = D == 3 ? a.fcut_x[(1 - fk) * stride + p0] : T(0);
+  T tk[PB], wq[PB];
+  auto load = [&](int pb) {
 #pragma unroll
-    for (int e = 0; e < ME; ++e) {
-      if (e < ne && (e == 0 || rank[e - 1] != rank[e])) {
-#pragma unroll
-        for (int j = 0; j < NPL; ++j) {
-          T s = acc[e][j];
-#pragma unroll
-          for (int e2 = e + 1; e2 < ME; ++e2)
-            if (e2 < ne && rank[e2] == rank[e]) s += acc[e2][j];
-          const int l = t + NT * j;
-          if (l < ND) v[(int64_t)rank[e] * ND + l] = s;
-        }
+    for (int i = 0; i < PB; ++i) {
+      tk[i] = 0; wq[i] = 0;
+      if (pb + i < n) {
+        const int64_t q = p0 + pb + i;
+        tk[i] = a.fcut_x[fk * stride + q];
+        wq[i] = a.fcut_w[q];
+        if (a.kappa) wq[i] *= a.kappa[a.seg[3] + q];
       }
     }
+  };
+  load(0);
+  T F[K], dF[K];
+  if constexpr (D == 3) {
+    lagrange1d<K>(Xn, ID, tf, F, dF);
+  } else {
+#pragma unroll
+    for (int i = 0; i < K; ++i) F[i] = 1;
+  }
+  // columns along the line: value and normal derivative, own and neighbour
+  T c0[K], cn[K], m0[K], mn[K];
+#pragma unroll
+  for (int lk = 0; lk < K; ++lk) {
+    T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+#pragma unroll
+    for (int f = 0; f < (D == 3 ? K : 1); ++f) {
+      // offset of (lk, f) within a normal layer: along A the line index is
+      // the A index (stride K), along B the B index (stride 1)
+      const int o = D == 3 ? (alongB ? lk + f * K : lk * K + f) : lk;
+      T s0 = 0, s1 = 0, r0 = 0, r1 = 0;
+#pragma unroll
+      for (int nn = 0; nn < K; ++nn) {
+        const T uo = Uo[nn * NF + o], un = Un[nn * NF + o];
+        s0 += Eo[nn] * uo;
+        s1 += Eo[K + nn] * uo;
+        r0 += En[nn] * un;
+        r1 += En[K + nn] * un;
+      }
+      a0 += F[f] * s0;
+      a1 += F[f] * s1;
+      b0 += F[f] * r0;
+      b1 += F[f] * r1;
+    }
+    asm volatile("" : "+v"(a0), "+v"(a1), "+v"(b0), "+v"(b1)::"memory");
+    c0[lk] = a0;
+    cn[lk] = a1;
+    m0[lk] = b0;
+    mn[lk] = b1;
+  }
+  T D0[K], DN[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) { D0[i] = 0; DN[i] = 0; }
+  for (int pb = 0; pb < n; pb += PB) {
+    if (pb > 0) load(pb);
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      if (pb + i >= n) break;
+      T Z[K], dZ[K];
+      lagrange1d<K>(Xn, ID, tk[i], Z, dZ);
+      T val = 0, go = 0, vn = 0, gn = 0;
+#pragma unroll
+      for (int ii = 0; ii < K; ++ii) {
+        val += Z[ii] * c0[ii];
+        go += Z[ii] * cn[ii];
+        vn += Z[ii] * m0[ii];
+        gn += Z[ii] * mn[ii];
+      }
+      // SIPG: jump sigma (u_own - u_nbr), average of the normal derivative
+      const T c = a.hs * wq[i];
+      const T J = sigma * (val - vn);
+      const T A = T(0.5) * (go + gn);
+      const T f0 = c * sigma * (a.gamma * J - A);
+      const T fn = T(-0.5) * c * J;
+#pragma unroll
+      for (int ii = 0; ii < K; ++ii) {
+        D0[ii] += Z[ii] * f0;
+        DN[ii] += Z[ii] * fn;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    if constexpr (D == 3) R[FS::VF + i] = F[i];
+    R[FS::D0 + i] = D0[i];
+    R[FS::DN + i] = DN[i];
+  }
+}
+
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+                                                      const int32_t* __restrict__ batches,
+                                                      const int32_t* __restrict__ entries,
+                                                      const int32_t* __restrict__ lines, int n_batches) {
+  using FW = FaceWork<K, D, T>;
+  using FS = FaceShape<K, D>;
+  constexpr int ND = FW::ND, ME = FW::ME, RS = FW::RS, RP = FW::RP, NT = BatchShape<K, D>::NT,
+                NPL = BatchShape<K, D>::NPL, NF = FS::NF;
+  constexpr int OFS = (1 << kBatchOffsetBits) - 1;
+  __shared__ FW W;
+  const int t = threadIdx.x;
+  for (int i = t; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
+  int dof_i[NPL][3];
+  lane_dofs<K, D, NPL>(dof_i);
+  for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
+    const int e0 = batches[4 * b], ne = batches[4 * b + 1], total = batches[4 * b + 2], l0 = batches[4 * b + 3];
+    if (t < 4 * ne) (&W.ent[0][0])[t] = entries[4 * e0 + t];
+    int2 hd = make_int2(0, 0);
+    if (t < total) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + t));
+    sync();
+    int rank[ME], ofs[ME + 1], nA[ME], slt[ME];
+#pragma unroll
+    for (int e = 0; e < ME; ++e) {
+      rank[e] = e < ne ? W.ent[e][0] : -1;
+      ofs[e] = e < ne ? (W.ent[e][2] & OFS) : total;
+      nA[e] = W.ent[e][1] & 0xffff;
+      slt[e] = W.ent[e][2] >> kBatchOffsetBits;
+    }
+    ofs[ME] = total;
+    // stage the DoFs of cell and neighbour, transposed to (N, A, B)
+    for (int idx = t; idx < ne * ND; idx += NT) {
+      const int e = idx / ND, l = idx % ND;
+      const int N = (W.ent[e][2] >> kBatchOffsetBits) >> 1;
+      const int d0 = l % K, d1 = (l / K) % K, d2 = D == 3 ? l / (K * K) : 0;
+      int tr;
+      if constexpr (D == 3) tr = N == 0 ? d0 * NF + d1 * K + d2 : (N == 1 ? d1 * NF + d0 * K + d2 : d2 * NF + d0 * K + d1);
+      else tr = N == 0 ? d0 * K + d1 : d1 * K + d0;
+      W.U[e][tr] = x[(int64_t)W.ent[e][0] * ND + l];
+      W.NB[e][tr] = x[(int64_t)W.ent[e][3] * ND + l];
+    }
+    T acc[ME][NPL];
+    batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
+    sync();
+    for (int base = 0; base < total; base += NT) {
+      const int g = base + t;
+      T R[RS];
+#pragma unroll
+      for (int c = 0; c < RS; ++c) R[c] = 0;
+      if (g < total) {
+        if (base > 0) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + g));
+        const int info = hd.y & 0xffffff, e = hd.y >> 24;
+        const int slot = W.ent[e][2] >> kBatchOffsetBits;
+        const bool alongB = ((info >> 16) & 0xf) == 1;  // in-face axis of the line
+        line_work_face<K, D>(W.tab, a, info, hd.x, slot, alongB, &W.U[0][0] + e * ND, &W.NB[0][0] + e * ND, R);
+      }
+#pragma unroll
+      for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = R[c];
+      sync();
+      const int r1 = min(total, base + NT);
+#pragma unroll
+      for (int e = 0; e < ME; ++e) {
+        if (e < ne && ofs[e] < r1 && ofs[e + 1] > base) {
+          const int N = slt[e] >> 1;
+          const int A = N == 0 ? 1 : 0, B = N == 2 ? 1 : 2;
+          const T* E = W.tab + ((slt[e] & 1) ? TabOff::E1(K) : TabOff::E0(K));
+#pragma unroll
+          for (int grp = 0; grp < (D == 3 ? 2 : 1); ++grp) {
+            const int lo = grp == 0 ? ofs[e] : ofs[e] + nA[e];
+            const int hi = grp == 0 ? ofs[e] + nA[e] : ofs[e + 1];
+            const int rlo = max(lo, base) - base, rhi = min(hi, r1) - base;
+            if (rlo >= rhi) continue;
+            const int LA = grp == 0 ? A : B, FA = grp == 0 ? B : A;
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+              auto pick = [&](int ax) { return ax == 0 ? dof_i[j][0] : (ax == 1 ? dof_i[j][1] : dof_i[j][2]); };
+              const int iN = pick(N), il = pick(LA), iF = pick(FA);
+              const T en = E[iN], den = E[K + iN];
+              const T* Rv = W.REC + (FS::VF + iF) * RP;
+              const T* R0 = W.REC + (FS::D0 + il) * RP;
+              const T* Rn = W.REC + (FS::DN + il) * RP;
+              T s = 0;
+#pragma unroll 1
+              for (int r = rlo; r < rhi; ++r) {
+                const T w = en * R0[r] + den * Rn[r];
+                s += D == 3 ? Rv[r] * w : w;
+              }
+              acc[e][j] += s;
+            }
+          }
+        }
+      }
+      sync();
+    }
+    batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
   }
 }
 
@@ -1797,10 +1921,10 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
         const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
         if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
         if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0)
-          cut_batch_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.vbatch, a.ventry,
+          cut_batch_kernel<K, D, T><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.vbatch, a.ventry,
                                                                                         a.vline, a.n_vbatch);
         if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0)
-          cut_batch_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.fbatch, a.fentry,
+          cut_face_kernel<K, D, T><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.fbatch, a.fentry,
                                                                                        a.fline, a.n_fbatch);
       }
     } else {
