@@ -120,9 +120,9 @@ struct ufem_op {
           *slot_face = nullptr, *face_qn = nullptr;
   int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
   int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
-          *line_info = nullptr, *cell_desc = nullptr, *vbatch = nullptr, *ventry = nullptr, *fbatch = nullptr,
-          *fentry = nullptr, *vline = nullptr, *fline = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
-  int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0;
+          *line_info = nullptr, *cell_desc = nullptr, *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr,
+          *fdesc = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
+  int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   // per-precision data
   struct Prec {
     void *vol_x = nullptr, *vol_w = nullptr, *surf_x = nullptr, *surf_w = nullptr, *surf_n = nullptr,
@@ -210,12 +210,11 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.line_first = line_first;
   a.line_info = line_info;
   a.cell_desc = cell_desc;
-  a.vbatch = vbatch;
-  a.ventry = ventry;
-  a.fbatch = fbatch;
-  a.fentry = fentry;
-  a.vline = vline;
-  a.fline = fline;
+  a.vbrec = vbrec;
+  a.vdesc = vdesc;
+  a.fbrec = fbrec;
+  a.fdesc = fdesc;
+  a.n_cu = n_cu;
   a.n_vbatch = n_vbatch;
   a.n_fbatch = n_fbatch;
   a.sf_bm = sf_bm;
@@ -383,6 +382,9 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     op->P = plan->P;
     op->device = device;
     op->max_bytes = max_device_bytes;
+    if (hipDeviceGetAttribute(&op->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        op->n_cu < 1)
+      op->n_cu = 1;
     const ufem::Plan& P = op->P;
     const int dim = P.dim, S = 2 * dim;
     const size_t na = P.active.size();
@@ -451,23 +453,30 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
     // line batches for the cut-cell kernels: cells (most work first) packed
     // into waves of at most 64 lines; a cell with more lines gets a wave of
-    // its own.  Per batch line descriptors (first point, line info | entry
-    // << 24), the lines of each entry ordered by cell axis.
+    // its own.  Fixed-size batch records and line descriptors (layout in
+    // device.hpp), the lines of each entry ordered by axis.
     bool batch_overflow = false;
-    auto make_batches = [&](bool face, std::vector<int32_t>& batches, std::vector<int32_t>& entries,
-                            std::vector<int32_t>& blines) {
+    auto make_batches = [&](bool face, std::vector<int32_t>& brec, std::vector<int32_t>& desc, int32_t& n_batches) {
       const int me = ufem::batch_max_entries((int)P.nd(), face);
-      int cur_lines = 0, cur_n = 0, first = 0;
+      const int nr = ufem::batch_record_ints(me);
+      std::vector<int32_t> rec, lines, ovf;  // current batch; overflow area
+      int cur_n = 0;
+      std::vector<int32_t> slots;            // first-round descriptors of all batches
       auto close = [&]() {
-        if (cur_n > 0) {
-          batches.push_back(first);
-          batches.push_back(cur_n);
-          batches.push_back(cur_lines);
-          batches.push_back((int32_t)(blines.size() / 2) - cur_lines);
+        if (cur_n == 0) return;
+        const int total = (int)lines.size() / 2;
+        rec[0] = cur_n;
+        rec[1] = total;
+        rec[2] = (int32_t)(ovf.size() / 2);
+        rec[3] = 0;
+        brec.insert(brec.end(), rec.begin(), rec.end());
+        for (int g = 0; g < ufem::kBatchLines; ++g) {
+          slots.push_back(g < total ? lines[2 * g] : 0);
+          slots.push_back(g < total ? lines[2 * g + 1] : 0);
         }
-        first = (int)(entries.size() / 4);
-        cur_lines = 0;
+        if (total > ufem::kBatchLines) ovf.insert(ovf.end(), lines.begin() + 2 * ufem::kBatchLines, lines.end());
         cur_n = 0;
+        lines.clear();
       };
       for (int32_t ci : order) {
         const int32_t r = P.cut[ci];
@@ -484,37 +493,47 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         }
         if (ce.empty()) continue;
         int nl = 0, n_e = (int)ce.size() / 4;
-        for (int e = 0; e < n_e; ++e) nl += ce[4 * e + 1] - ce[4 * e];
-        if (cur_n > 0 && (cur_lines + nl > ufem::kBatchLines || cur_n + n_e > me)) close();
-        for (int e = 0; e < n_e; ++e)
+        for (int e = 0; e < n_e; ++e) {
+          nl += ce[4 * e + 1] - ce[4 * e];
           if (face && ce[4 * e + 3] < 0) batch_overflow = true;  // a cut face always has a neighbour
-        if (batch_overflow || n_e > me || cur_lines + nl >= (1 << ufem::kBatchOffsetBits)) {
+        }
+        const int cur_lines = (int)lines.size() / 2;
+        if (cur_n > 0 && (cur_lines + nl > ufem::kBatchLines || cur_n + n_e > me)) close();
+        if (batch_overflow || n_e > me || nl >= (1 << ufem::kBatchOffsetBits)) {
           batch_overflow = true;
           return;
         }
+        if (cur_n == 0) rec.assign(nr, 0);
         for (int e = 0; e < n_e; ++e) {
           const int32_t lb = ce[4 * e], le = ce[4 * e + 1], sl = ce[4 * e + 2];
           // volume lines by cell axis, face lines by in-face axis (the same
           // order, the in-face axes being the other cell axes ascending)
           int cnt[3] = {0, 0, 0};
+          const int first = (int)lines.size() / 2;
           for (int ax = 0; ax < P.dim; ++ax)
             for (int32_t l = lb; l < le; ++l) {
               if (P.line_axis[l] != ax) continue;
-              blines.push_back((int32_t)P.line_first[l]);
-              blines.push_back(linfo[l] | ((cur_n + e) << 24));
+              lines.push_back((int32_t)P.line_first[l]);
+              lines.push_back(linfo[l] | ((cur_n + e) << 24));
               ++cnt[ax];
             }
           if (cnt[0] > 0xffff || cnt[1] > 0xffff) {
             batch_overflow = true;
             return;
           }
-          entries.insert(entries.end(), {r, cnt[0] | (cnt[1] << 16), cur_lines | (sl << ufem::kBatchOffsetBits), ce[4 * e + 3]});
-          cur_lines += le - lb;
+          int32_t* en = &rec[4 + 4 * (cur_n + e)];
+          en[0] = r;
+          en[1] = cnt[0] | (cnt[1] << 16);
+          en[2] = first | (sl << ufem::kBatchOffsetBits);
+          en[3] = ce[4 * e + 3];
         }
         cur_n += n_e;
-        if (cur_lines >= ufem::kBatchLines) close();
+        if ((int)lines.size() / 2 >= ufem::kBatchLines) close();
       }
       close();
+      n_batches = (int32_t)(brec.size() / nr);
+      desc = std::move(slots);
+      desc.insert(desc.end(), ovf.begin(), ovf.end());
     };
     std::vector<int32_t> sbm, sbp, sax;
     for (const ufem::Face& f : P.faces)
@@ -524,15 +543,13 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         sax.push_back(f.axis);
       }
     op->n_sfaces = (int32_t)sbm.size();
-    std::vector<int32_t> vb, ve, vl, fb, fe, fl;
-    make_batches(false, vb, ve, vl);
-    make_batches(true, fb, fe, fl);
+    std::vector<int32_t> vb, vl, fb, fl;
+    make_batches(false, vb, vl, op->n_vbatch);
+    make_batches(true, fb, fl, op->n_fbatch);
     if (batch_overflow) {
       delete op;
       return fail(UFEM_EUNSUPPORTED, "ufem_setup: a cut cell has more lines or cut faces than one line batch holds");
     }
-    op->n_vbatch = (int32_t)(vb.size() / 4);
-    op->n_fbatch = (int32_t)(fb.size() / 4);
     int rc;
     if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->cut_order, order)) ||
         (rc = op->upload((void**)&op->cut_rank, P.cut)) || (rc = op->upload((void**)&op->nb, nb)) ||
@@ -542,9 +559,8 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->cell_line_off, cloff)) || (rc = op->upload((void**)&op->face_lbeg, flb)) ||
         (rc = op->upload((void**)&op->face_lend, fle)) || (rc = op->upload((void**)&op->line_first, P.line_first)) ||
         (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc)) ||
-        (rc = op->upload((void**)&op->vbatch, vb)) || (rc = op->upload((void**)&op->ventry, ve)) ||
-        (rc = op->upload((void**)&op->fbatch, fb)) || (rc = op->upload((void**)&op->fentry, fe)) ||
-        (rc = op->upload((void**)&op->vline, vl)) || (rc = op->upload((void**)&op->fline, fl)) ||
+        (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
+        (rc = op->upload((void**)&op->fbrec, fb)) || (rc = op->upload((void**)&op->fdesc, fl)) ||
         (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||
         (rc = op->upload((void**)&op->sf_ax, sax))) {
       delete op;

@@ -25,16 +25,21 @@ constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
 //   M [K*K]   1D mass matrix of the GLL Lagrange basis (exact: Gauss rule)
 //   KS[K*K]   1D stiffness matrix of the GLL Lagrange basis
 //   DS[K*K]   DS[q*K+i] = L_i'(g_q), GLL basis derivative at the Gauss points
-// Line batches of the cut-cell kernels.  Batch b = (first entry, entries,
-// lines, first line descriptor).  Entry = (active rank of the cell, lines
-// along axis 0 | lines along axis 1 << 16, offset of the entry's first line
-// in the batch | slot << 24, active rank of the neighbour across the slot or
-// -1).  Line descriptor = (first point, count | axis << 16 | kind << 20 |
-// entry << 24); the lines of an entry are consecutive and ordered by axis.
-// Axes are cell axes for volume / interface entries (slot 15) and in-face
-// axes for cut-face entries (one per cut face of a cut cell).  Entries of one
-// cell are consecutive and in one batch.
+// Line batches of the cut-cell kernels.  Batch b has a record of
+// batch_record_ints(ME) ints at a fixed stride: (entries, lines, offset of
+// its descriptors beyond the first kBatchLines in the overflow area, 0), then
+// ME entries of 4 ints: (active rank of the cell, lines along axis 0 | lines
+// along axis 1 << 16, offset of the entry's first line in the batch | slot <<
+// 24, active rank of the neighbour across the slot or -1).  Line descriptors
+// are int pairs (first point, count | axis << 16 | kind << 20 | entry << 24):
+// the first kBatchLines of batch b at [b * kBatchLines, ...) (unused slots
+// zero), the rest in the overflow area after n_batches * kBatchLines.  The
+// lines of an entry are consecutive and ordered by axis: cell axes for
+// volume / interface entries (slot 15), in-face axes for cut-face entries
+// (one per cut face of a cut cell).  Entries of one cell are consecutive and
+// in one batch.
 constexpr __host__ __device__ int batch_max_entries(int, bool face) { return face ? 12 : 8; }
+constexpr __host__ __device__ int batch_record_ints(int me) { return 4 + 4 * me; }
 constexpr int kBatchLines = 64;        // lines per round (one per lane)
 constexpr int kBatchOffsetBits = 24;   // bits of the in-batch line offset
 
@@ -70,16 +75,14 @@ struct DevArgs {
   const int32_t* line_first;     // first point of a line
   const int32_t* line_info;      // count | axis << 16 | kind << 20
   const int32_t* cell_desc;      // [n_cut * 24] line segments of each cut cell
-  // line batches (layout above): volume / interface lines of cut cells
-  // (slot 15, no neighbour) and cut-face lines (one entry per cut face of a
-  // cut cell, slot of the face)
-  const int32_t* vbatch;
-  const int32_t* ventry;
-  const int32_t* fbatch;
-  const int32_t* fentry;
-  const int32_t* vline;  // line descriptors, pairs
-  const int32_t* fline;
+  // line batches (layout above): volume / interface lines of cut cells and
+  // cut-face lines; records and line descriptors
+  const int32_t* vbrec;
+  const int32_t* vdesc;
+  const int32_t* fbrec;
+  const int32_t* fdesc;
   int32_t n_vbatch, n_fbatch;
+  int32_t n_cu;  // compute units of the device (persistent grids)
   // structured SIPG faces (kappa order): ranks of the lower / upper cell, axis
   const int32_t* sf_bm;
   const int32_t* sf_bp;

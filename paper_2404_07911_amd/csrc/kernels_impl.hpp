@@ -43,6 +43,15 @@ struct Shape {
 
 __device__ __forceinline__ void sync() { __syncthreads(); }
 
+// Workgroups of exactly one wavefront: the LDS operations of a wavefront are
+// performed in issue order, so only the compiler has to be kept from moving
+// memory accesses across this point (no s_barrier, and no wait for
+// outstanding global loads, which may stay in flight).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // out = M (or M^T) applied along axis AX of a K^N tensor
 template <int K, int N, int AX, bool TR, bool ACC, typename T>
 __device__ __forceinline__ void contract(const T* __restrict__ M, const T* in, T* out) {
@@ -995,70 +1004,83 @@ __device__ __forceinline__ void line_columns(const T* u, const T* V1, const T* d
   }
 }
 
-// store a line record (layout of LineShape)
-template <int K, int D, typename T>
+// store a line record (layout of LineShape) into column r of REC (pitch RP)
+template <int K, int D, int RP, typename T>
 __device__ __forceinline__ void line_record(const T* V1, const T* dV1, const T* V2, const T* dV2, const T* D0,
-                                            const T* D1, const T* D2, T* R) {
+                                            const T* D1, const T* D2, T* REC, int r) {
   using LS = LineShape<K, D>;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    R[LS::V1 + i] = V1[i];
-    R[LS::DV1 + i] = dV1[i];
-    R[LS::D0 + i] = D0[i];
-    R[LS::D1 + i] = D1[i];
+    REC[(LS::V1 + i) * RP + r] = V1[i];
+    REC[(LS::DV1 + i) * RP + r] = dV1[i];
+    REC[(LS::D0 + i) * RP + r] = D0[i];
+    REC[(LS::D1 + i) * RP + r] = D1[i];
     if constexpr (D == 3) {
-      R[LS::V2 + i] = V2[i];
-      R[LS::DV2 + i] = dV2[i];
-      R[LS::D2 + i] = D2[i];
+      REC[(LS::V2 + i) * RP + r] = V2[i];
+      REC[(LS::DV2 + i) * RP + r] = dV2[i];
+      REC[(LS::D2 + i) * RP + r] = D2[i];
     }
   }
 }
 
-// one volume or interface line of points along cell axis KA: evaluate,
-// apply the point flux, integrate along the line; leaves the line record in
-// R.  info / p0: the line descriptor (count | axis << 16 | kind << 20, first
-// point)
-template <int K, int D, int KA, typename T>
-__device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a, int info, int p0, const T* Uo,
-                                               T* R) {
-  constexpr int O1 = KA == 0 ? 1 : 0;
-  constexpr int O2 = KA == 2 ? 1 : 2;
-  constexpr int PB = 4;  // points whose data is loaded in one round
-  const T* Xn = tab + TabOff::X(K);
-  const T* ID = tab + TabOff::ID(K);
+// Point data of a line, loaded ahead of the arithmetic: the two fixed
+// coordinates, and for the first PB points the coordinate along the line,
+// the weight (times kappa) and, on interface lines, the normal.
+constexpr int kLinePB = 4;
+template <typename T>
+struct LinePts {
+  T t1, t2;
+  T tk[kLinePB], wq[kLinePB], nk[kLinePB], n1[kLinePB], n2[kLinePB];
+};
+
+// loads of points [pb, pb + PB) of a volume / interface line along cell axis
+// ax (runtime) starting at point p0; fixed coordinates when pb == 0
+template <int D, typename T>
+__device__ __forceinline__ void line_load_cell(const DevArgs<T>& a, int info, int p0, int pb, LinePts<T>& L) {
   const int n = info & 0xffff;
+  const int ax = (info >> 16) & 0xf;
   const bool surf = ((info >> 20) & 0xf) == 1;
+  const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
   const T* px = surf ? a.surf_x : a.vol_x;
   const int64_t stride = surf ? a.n_surf : a.n_vol;
   const T* pw = surf ? a.surf_w : a.vol_w;
   const int64_t kbase = surf ? a.seg[4] : a.seg[1];
-  // every global load of the line's first PB points is issued before any
-  // arithmetic
-  const T t1 = px[O1 * stride + p0];
-  const T t2 = D == 3 ? px[O2 * stride + p0] : T(0);
-  T tk[PB], wq[PB], nvk[PB], nv1[PB], nv2[PB];
-  auto load = [&](int pb) {
+  if (pb == 0) {
+    L.t1 = px[o1 * stride + p0];
+    L.t2 = D == 3 ? px[o2 * stride + p0] : T(0);
+  }
 #pragma unroll
-    for (int i = 0; i < PB; ++i) {
-      tk[i] = 0; wq[i] = 0; nvk[i] = 0; nv1[i] = 0; nv2[i] = 0;
-      if (pb + i < n) {
-        const int64_t q = p0 + pb + i;
-        tk[i] = px[KA * stride + q];
-        wq[i] = pw[q];
-        if (a.kappa) wq[i] *= a.kappa[kbase + q];
-        if (surf) {
-          nvk[i] = a.surf_n[KA * stride + q];
-          nv1[i] = a.surf_n[O1 * stride + q];
-          if constexpr (D == 3) nv2[i] = a.surf_n[O2 * stride + q];
-        }
+  for (int i = 0; i < kLinePB; ++i) {
+    L.tk[i] = 0; L.wq[i] = 0; L.nk[i] = 0; L.n1[i] = 0; L.n2[i] = 0;
+    if (pb + i < n) {
+      const int64_t q = p0 + pb + i;
+      L.tk[i] = px[ax * stride + q];
+      L.wq[i] = pw[q];
+      if (a.kappa) L.wq[i] *= a.kappa[kbase + q];
+      if (surf) {
+        L.nk[i] = a.surf_n[ax * stride + q];
+        L.n1[i] = a.surf_n[o1 * stride + q];
+        if constexpr (D == 3) L.n2[i] = a.surf_n[o2 * stride + q];
       }
     }
-  };
-  load(0);
+  }
+}
+
+// one volume or interface line of points along cell axis KA whose first
+// point data are in L: evaluate, apply the point flux, integrate along the
+// line; writes the line record to column r of REC.  info / p0: the line
+// descriptor (count | axis << 16 | kind << 20, first point)
+template <int K, int D, int KA, int RP, typename T>
+__device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a, int info, int p0, LinePts<T>& L,
+                                               const T* Uo, T* REC, int r) {
+  const T* Xn = tab + TabOff::X(K);
+  const T* ID = tab + TabOff::ID(K);
+  const int n = info & 0xffff;
+  const bool surf = ((info >> 20) & 0xf) == 1;
   T V1[K], dV1[K], V2[K], dV2[K];
-  lagrange1d<K>(Xn, ID, t1, V1, dV1);
+  lagrange1d<K>(Xn, ID, L.t1, V1, dV1);
   if constexpr (D == 3) {
-    lagrange1d<K>(Xn, ID, t2, V2, dV2);
+    lagrange1d<K>(Xn, ID, L.t2, V2, dV2);
   } else {
 #pragma unroll
     for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; }
@@ -1068,13 +1090,13 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
   T D0[K], D1[K], D2[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) { D0[i] = 0; D1[i] = 0; D2[i] = 0; }
-  for (int pb = 0; pb < n; pb += PB) {
-    if (pb > 0) load(pb);
+  for (int pb = 0; pb < n; pb += kLinePB) {
+    if (pb > 0) line_load_cell<D>(a, info, p0, pb, L);
 #pragma unroll
-    for (int i = 0; i < PB; ++i) {
+    for (int i = 0; i < kLinePB; ++i) {
       if (pb + i >= n) break;
       T Z[K], dZ[K];
-      lagrange1d<K>(Xn, ID, tk[i], Z, dZ);
+      lagrange1d<K>(Xn, ID, L.tk[i], Z, dZ);
       T val = 0, gk = 0, g1 = 0, g2 = 0;
 #pragma unroll
       for (int ii = 0; ii < K; ++ii) {
@@ -1083,15 +1105,15 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
         g1 += Z[ii] * c1[ii];
         g2 += Z[ii] * c2[ii];
       }
-      const T c = a.hs * wq[i];
+      const T c = a.hs * L.wq[i];
       T f0, fk, f1, f2;
       if (surf) {
         // Nitsche: tau u v - d_n u v - u d_n v
-        const T dn = nvk[i] * gk + nv1[i] * g1 + nv2[i] * g2;
+        const T dn = L.nk[i] * gk + L.n1[i] * g1 + L.n2[i] * g2;
         f0 = c * (a.tau * val - dn);
-        fk = -c * val * nvk[i];
-        f1 = -c * val * nv1[i];
-        f2 = -c * val * nv2[i];
+        fk = -c * val * L.nk[i];
+        f1 = -c * val * L.n1[i];
+        f2 = -c * val * L.n2[i];
       } else {
         f0 = 0;
         fk = c * gk;
@@ -1106,7 +1128,7 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
       }
     }
   }
-  line_record<K, D>(V1, dV1, V2, dV2, D0, D1, D2, R);
+  line_record<K, D, RP>(V1, dV1, V2, dV2, D0, D1, D2, REC, r);
 }
 
 // Batched line kernels: one wave per batch of cut cells whose lines fit in
@@ -1114,7 +1136,10 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
 // Each lane keeps the sums of its DoFs for every entry of the batch in
 // registers; the records of a round pass through LDS, and as the lines of
 // an entry come ordered by axis, the reduction reads them with fixed index
-// patterns.
+// patterns.  The grid is persistent: while a wave works on one batch, the
+// batch record and the first-round line descriptors of its next batch are
+// already in flight, and the point data of a round are loaded together with
+// the cell DoFs.
 template <int K, int D>
 struct BatchShape {
   static constexpr int ND = ipow(K, D);
@@ -1170,6 +1195,31 @@ __device__ __forceinline__ void batch_acc_store(T* __restrict__ v, const int* ra
   }
 }
 
+// the batch record (header and entries, batch_record_ints(ME) ints at a
+// fixed stride) and the lane's first-round line descriptor
+struct BatchFetch {
+  int rec;
+  int2 hd;
+};
+
+template <int ME>
+__device__ __forceinline__ BatchFetch batch_fetch(const int32_t* __restrict__ brec, const int32_t* __restrict__ desc,
+                                                  int b, int n_batches) {
+  constexpr int NR = batch_record_ints(ME);
+  BatchFetch f{0, make_int2(0, 0)};
+  if (b < n_batches) {
+    const int t = threadIdx.x;
+    if (t < NR) f.rec = brec[(int64_t)b * NR + t];
+    f.hd = *reinterpret_cast<const int2*>(desc + 2 * ((int64_t)b * kBatchLines + t));
+  }
+  return f;
+}
+
+// line descriptor of in-batch line g >= kBatchLines
+__device__ __forceinline__ int2 batch_desc(const int32_t* __restrict__ desc, int n_batches, int ovf, int g) {
+  return *reinterpret_cast<const int2*>(desc + 2 * ((int64_t)n_batches * kBatchLines + ovf + g - kBatchLines));
+}
+
 // ---- volume and interface lines
 template <int K, int D, typename T>
 struct BatchWork {
@@ -1178,7 +1228,7 @@ struct BatchWork {
   T tab[TabOff::size(K)];
   T U[ME][ND];
   T REC[RS * RP];  // component c of the round's record r at REC[c * RP + r]
-  int ent[ME][4];
+  int rec[batch_record_ints(ME)];
 };
 
 // acc += the records [lo, hi) of the round, all along axis KA
@@ -1188,33 +1238,36 @@ __device__ __forceinline__ void reduce_axis(const T* REC, int lo, int hi, const 
   constexpr int P = BatchShape<K, D>::RP;
   constexpr int O1 = KA == 0 ? 1 : 0;
   constexpr int O2 = KA == 2 ? 1 : 2;
-#pragma unroll 1
-  for (int r = lo; r < hi; ++r) {
-    const T* Rc = REC + r;
 #pragma unroll
-    for (int j = 0; j < NPL; ++j) {
-      const int ik = dof_i[j][KA], i1 = dof_i[j][O1];
-      const T v1 = Rc[(LS::V1 + i1) * P], dv1 = Rc[(LS::DV1 + i1) * P];
-      const T d0 = Rc[(LS::D0 + ik) * P], d1 = Rc[(LS::D1 + ik) * P];
-      if constexpr (D == 3) {
-        const int i2 = dof_i[j][O2];
-        const T v2 = Rc[(LS::V2 + i2) * P], dv2 = Rc[(LS::DV2 + i2) * P], d2 = Rc[(LS::D2 + ik) * P];
-        acc[j] += v2 * (v1 * d0 + dv1 * d1) + v1 * dv2 * d2;
-      } else {
-        acc[j] += v1 * d0 + dv1 * d1;
-      }
+  for (int j = 0; j < NPL; ++j) {
+    const int ik = dof_i[j][KA], i1 = dof_i[j][O1];
+    const T* Rv1 = REC + (LS::V1 + i1) * P;
+    const T* Rdv1 = REC + (LS::DV1 + i1) * P;
+    const T* Rd0 = REC + (LS::D0 + ik) * P;
+    const T* Rd1 = REC + (LS::D1 + ik) * P;
+    T s = 0;
+    if constexpr (D == 3) {
+      const int i2 = dof_i[j][O2];
+      const T* Rv2 = REC + (LS::V2 + i2) * P;
+      const T* Rdv2 = REC + (LS::DV2 + i2) * P;
+      const T* Rd2 = REC + (LS::D2 + ik) * P;
+#pragma unroll 2
+      for (int r = lo; r < hi; ++r) s += Rv2[r] * (Rv1[r] * Rd0[r] + Rdv1[r] * Rd1[r]) + Rv1[r] * Rdv2[r] * Rd2[r];
+    } else {
+#pragma unroll 2
+      for (int r = lo; r < hi; ++r) s += Rv1[r] * Rd0[r] + Rdv1[r] * Rd1[r];
     }
+    acc[j] += s;
   }
 }
 
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
-                                                       const int32_t* __restrict__ batches,
-                                                       const int32_t* __restrict__ entries,
-                                                       const int32_t* __restrict__ lines, int n_batches) {
+                                                       const int32_t* __restrict__ brec,
+                                                       const int32_t* __restrict__ desc, int n_batches) {
   using BW = BatchWork<K, D, T>;
   constexpr int ND = BW::ND, ME = BW::ME, RS = BW::RS, RP = BW::RP, NT = BatchShape<K, D>::NT,
-                NPL = BatchShape<K, D>::NPL;
+                NPL = BatchShape<K, D>::NPL, NR = batch_record_ints(ME);
   constexpr int OFS = (1 << kBatchOffsetBits) - 1;
   __shared__ BW W;
   const int t = threadIdx.x;
@@ -1222,49 +1275,58 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
   const bool do_vol = (a.terms & 1) != 0, do_surf = (a.terms & 4) != 0;
   int dof_i[NPL][3];
   lane_dofs<K, D, NPL>(dof_i);
+  BatchFetch nxt = batch_fetch<ME>(brec, desc, blockIdx.x, n_batches);
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
-    const int e0 = batches[4 * b], ne = batches[4 * b + 1], total = batches[4 * b + 2], l0 = batches[4 * b + 3];
-    if (t < 4 * ne) (&W.ent[0][0])[t] = entries[4 * e0 + t];
-    // descriptor of the lane's line in the first round
-    int2 hd = make_int2(0, 0);
-    if (t < total) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + t));
-    sync();
+    const BatchFetch cur = nxt;
+    if (t < NR) W.rec[t] = cur.rec;
+    wave_sync();
+    nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
+    const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
+    const int* ent = W.rec + 4;
     int rank[ME], ofs[ME + 1], n0[ME], n1[ME];
 #pragma unroll
     for (int e = 0; e < ME; ++e) {
-      rank[e] = e < ne ? W.ent[e][0] : -1;
-      ofs[e] = e < ne ? (W.ent[e][2] & OFS) : total;
-      n0[e] = W.ent[e][1] & 0xffff;
-      n1[e] = (W.ent[e][1] >> 16) & 0xffff;
+      rank[e] = e < ne ? ent[4 * e] : -1;
+      ofs[e] = e < ne ? (ent[4 * e + 2] & OFS) : total;
+      n0[e] = ent[4 * e + 1] & 0xffff;
+      n1[e] = (ent[4 * e + 1] >> 16) & 0xffff;
     }
     ofs[ME] = total;
+    // point data of the first round, DoFs and rows of v in one round trip
+    int2 hd = cur.hd;
+    LinePts<T> L;
+    if (t < total) line_load_cell<D>(a, hd.y & 0xffffff, hd.x, 0, L);
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
-      W.U[e][l] = x[(int64_t)W.ent[e][0] * ND + l];
+      W.U[e][l] = x[(int64_t)ent[4 * e] * ND + l];
     }
     T acc[ME][NPL];
     batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
-    sync();
+    wave_sync();
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
-      T R[RS];
-#pragma unroll
-      for (int c = 0; c < RS; ++c) R[c] = 0;
+      bool done = false;
       if (g < total) {
-        if (base > 0) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + g));
+        if (base > 0) {
+          hd = batch_desc(desc, n_batches, ovf, g);
+          line_load_cell<D>(a, hd.y & 0xffffff, hd.x, 0, L);
+        }
         const int info = hd.y & 0xffffff, e = hd.y >> 24;
         const int kind = (info >> 20) & 0xf;
         const int ax = (info >> 16) & 0xf;
         const T* Uo = &W.U[0][0] + e * ND;
         if (kind == 0 ? do_vol : do_surf) {
-          if (ax == 0) line_work_cell<K, D, 0>(W.tab, a, info, hd.x, Uo, R);
-          else if (ax == 1 || D == 2) line_work_cell<K, D, 1>(W.tab, a, info, hd.x, Uo, R);
-          else if constexpr (D == 3) line_work_cell<K, D, 2>(W.tab, a, info, hd.x, Uo, R);
+          done = true;
+          if (ax == 0) line_work_cell<K, D, 0, RP>(W.tab, a, info, hd.x, L, Uo, W.REC, t);
+          else if (ax == 1 || D == 2) line_work_cell<K, D, 1, RP>(W.tab, a, info, hd.x, L, Uo, W.REC, t);
+          else if constexpr (D == 3) line_work_cell<K, D, 2, RP>(W.tab, a, info, hd.x, L, Uo, W.REC, t);
         }
       }
+      if (!done) {
 #pragma unroll
-      for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = R[c];
-      sync();
+        for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
+      }
+      wave_sync();
       const int r1 = min(total, base + NT);
 #pragma unroll
       for (int e = 0; e < ME; ++e) {
@@ -1275,7 +1337,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
           if constexpr (D == 3) reduce_axis<K, D, 2, NPL>(W.REC, max(a2, base) - base, min(a3, r1) - base, dof_i, acc[e]);
         }
       }
-      sync();
+      wave_sync();
     }
     batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
   }
@@ -1306,47 +1368,50 @@ struct FaceWork {
   static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), true),
                        RS = FaceShape<K, D>::RS, RP = BatchShape<K, D>::RP;
   T tab[TabOff::size(K)];
-  T U[ME][ND];   // transposed: U[e][iN * K^(D-1) + iA * K^(D-2) + iB]
+  T U[ME][ND];  // transposed: U[e][iN * K^(D-1) + iA * K^(D-2) + iB]
   T NB[ME][ND];
   T REC[RS * RP];
-  int ent[ME][4];
+  int rec[batch_record_ints(ME)];
 };
 
+// point data of a cut-face line: the coordinate along the other in-face
+// axis, and for points [pb, pb + PB) the coordinate along the line and the
+// weight (times kappa)
+template <int D, typename T>
+__device__ __forceinline__ void line_load_face(const DevArgs<T>& a, int info, int p0, int pb, LinePts<T>& L) {
+  const int n = info & 0xffff;
+  const int fk = (info >> 16) & 0xf;  // in-face axis of the line
+  const int64_t stride = a.n_fcut;
+  if (pb == 0) L.t1 = D == 3 ? a.fcut_x[(1 - fk) * stride + p0] : T(0);
+#pragma unroll
+  for (int i = 0; i < kLinePB; ++i) {
+    L.tk[i] = 0; L.wq[i] = 0;
+    if (pb + i < n) {
+      const int64_t q = p0 + pb + i;
+      L.tk[i] = a.fcut_x[fk * stride + q];
+      L.wq[i] = a.fcut_w[q];
+      if (a.kappa) L.wq[i] *= a.kappa[a.seg[3] + q];
+    }
+  }
+}
+
 // one cut-face line, along in-face axis A (alongB false) or B
-template <int K, int D, typename T>
+template <int K, int D, int RP, typename T>
 __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a, int info, int p0, int slot,
-                                               bool alongB, const T* Uo, const T* Un, T* R) {
+                                               LinePts<T>& L, const T* Uo, const T* Un, T* REC, int r) {
   using FS = FaceShape<K, D>;
-  constexpr int PB = 4;
   constexpr int NF = FS::NF;
   const T* Xn = tab + TabOff::X(K);
   const T* ID = tab + TabOff::ID(K);
   const int n = info & 0xffff;
+  const bool alongB = ((info >> 16) & 0xf) == 1;
   const int side = slot & 1;
   const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
   const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
   const T sigma = side ? T(1) : T(-1);
-  const int64_t stride = a.n_fcut;
-  // in-face coordinates: index 0 along A, 1 along B
-  const int fk = alongB ? 1 : 0;
-  const T tf = D == 3 ? a.fcut_x[(1 - fk) * stride + p0] : T(0);
-  T tk[PB], wq[PB];
-  auto load = [&](int pb) {
-#pragma unroll
-    for (int i = 0; i < PB; ++i) {
-      tk[i] = 0; wq[i] = 0;
-      if (pb + i < n) {
-        const int64_t q = p0 + pb + i;
-        tk[i] = a.fcut_x[fk * stride + q];
-        wq[i] = a.fcut_w[q];
-        if (a.kappa) wq[i] *= a.kappa[a.seg[3] + q];
-      }
-    }
-  };
-  load(0);
   T F[K], dF[K];
   if constexpr (D == 3) {
-    lagrange1d<K>(Xn, ID, tf, F, dF);
+    lagrange1d<K>(Xn, ID, L.t1, F, dF);
   } else {
 #pragma unroll
     for (int i = 0; i < K; ++i) F[i] = 1;
@@ -1384,13 +1449,13 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
   T D0[K], DN[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) { D0[i] = 0; DN[i] = 0; }
-  for (int pb = 0; pb < n; pb += PB) {
-    if (pb > 0) load(pb);
+  for (int pb = 0; pb < n; pb += kLinePB) {
+    if (pb > 0) line_load_face<D>(a, info, p0, pb, L);
 #pragma unroll
-    for (int i = 0; i < PB; ++i) {
+    for (int i = 0; i < kLinePB; ++i) {
       if (pb + i >= n) break;
       T Z[K], dZ[K];
-      lagrange1d<K>(Xn, ID, tk[i], Z, dZ);
+      lagrange1d<K>(Xn, ID, L.tk[i], Z, dZ);
       T val = 0, go = 0, vn = 0, gn = 0;
 #pragma unroll
       for (int ii = 0; ii < K; ++ii) {
@@ -1400,7 +1465,7 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
         gn += Z[ii] * mn[ii];
       }
       // SIPG: jump sigma (u_own - u_nbr), average of the normal derivative
-      const T c = a.hs * wq[i];
+      const T c = a.hs * L.wq[i];
       const T J = sigma * (val - vn);
       const T A = T(0.5) * (go + gn);
       const T f0 = c * sigma * (a.gamma * J - A);
@@ -1414,71 +1479,76 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
   }
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    if constexpr (D == 3) R[FS::VF + i] = F[i];
-    R[FS::D0 + i] = D0[i];
-    R[FS::DN + i] = DN[i];
+    if constexpr (D == 3) REC[(FS::VF + i) * RP + r] = F[i];
+    REC[(FS::D0 + i) * RP + r] = D0[i];
+    REC[(FS::DN + i) * RP + r] = DN[i];
   }
 }
 
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
-                                                      const int32_t* __restrict__ batches,
-                                                      const int32_t* __restrict__ entries,
-                                                      const int32_t* __restrict__ lines, int n_batches) {
+                                                      const int32_t* __restrict__ brec,
+                                                      const int32_t* __restrict__ desc, int n_batches) {
   using FW = FaceWork<K, D, T>;
   using FS = FaceShape<K, D>;
   constexpr int ND = FW::ND, ME = FW::ME, RS = FW::RS, RP = FW::RP, NT = BatchShape<K, D>::NT,
-                NPL = BatchShape<K, D>::NPL, NF = FS::NF;
+                NPL = BatchShape<K, D>::NPL, NF = FS::NF, NR = batch_record_ints(ME);
   constexpr int OFS = (1 << kBatchOffsetBits) - 1;
   __shared__ FW W;
   const int t = threadIdx.x;
   for (int i = t; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   int dof_i[NPL][3];
   lane_dofs<K, D, NPL>(dof_i);
+  BatchFetch nxt = batch_fetch<ME>(brec, desc, blockIdx.x, n_batches);
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
-    const int e0 = batches[4 * b], ne = batches[4 * b + 1], total = batches[4 * b + 2], l0 = batches[4 * b + 3];
-    if (t < 4 * ne) (&W.ent[0][0])[t] = entries[4 * e0 + t];
-    int2 hd = make_int2(0, 0);
-    if (t < total) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + t));
-    sync();
+    const BatchFetch cur = nxt;
+    if (t < NR) W.rec[t] = cur.rec;
+    wave_sync();
+    nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
+    const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
+    const int* ent = W.rec + 4;
     int rank[ME], ofs[ME + 1], nA[ME], slt[ME];
 #pragma unroll
     for (int e = 0; e < ME; ++e) {
-      rank[e] = e < ne ? W.ent[e][0] : -1;
-      ofs[e] = e < ne ? (W.ent[e][2] & OFS) : total;
-      nA[e] = W.ent[e][1] & 0xffff;
-      slt[e] = W.ent[e][2] >> kBatchOffsetBits;
+      rank[e] = e < ne ? ent[4 * e] : -1;
+      ofs[e] = e < ne ? (ent[4 * e + 2] & OFS) : total;
+      nA[e] = ent[4 * e + 1] & 0xffff;
+      slt[e] = ent[4 * e + 2] >> kBatchOffsetBits;
     }
     ofs[ME] = total;
+    int2 hd = cur.hd;
+    LinePts<T> L;
+    if (t < total) line_load_face<D>(a, hd.y & 0xffffff, hd.x, 0, L);
     // stage the DoFs of cell and neighbour, transposed to (N, A, B)
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
-      const int N = (W.ent[e][2] >> kBatchOffsetBits) >> 1;
+      const int N = (ent[4 * e + 2] >> kBatchOffsetBits) >> 1;
       const int d0 = l % K, d1 = (l / K) % K, d2 = D == 3 ? l / (K * K) : 0;
       int tr;
       if constexpr (D == 3) tr = N == 0 ? d0 * NF + d1 * K + d2 : (N == 1 ? d1 * NF + d0 * K + d2 : d2 * NF + d0 * K + d1);
       else tr = N == 0 ? d0 * K + d1 : d1 * K + d0;
-      W.U[e][tr] = x[(int64_t)W.ent[e][0] * ND + l];
-      W.NB[e][tr] = x[(int64_t)W.ent[e][3] * ND + l];
+      W.U[e][tr] = x[(int64_t)ent[4 * e] * ND + l];
+      W.NB[e][tr] = x[(int64_t)ent[4 * e + 3] * ND + l];
     }
     T acc[ME][NPL];
     batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
-    sync();
+    wave_sync();
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
-      T R[RS];
-#pragma unroll
-      for (int c = 0; c < RS; ++c) R[c] = 0;
       if (g < total) {
-        if (base > 0) hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + g));
+        if (base > 0) {
+          hd = batch_desc(desc, n_batches, ovf, g);
+          line_load_face<D>(a, hd.y & 0xffffff, hd.x, 0, L);
+        }
         const int info = hd.y & 0xffffff, e = hd.y >> 24;
-        const int slot = W.ent[e][2] >> kBatchOffsetBits;
-        const bool alongB = ((info >> 16) & 0xf) == 1;  // in-face axis of the line
-        line_work_face<K, D>(W.tab, a, info, hd.x, slot, alongB, &W.U[0][0] + e * ND, &W.NB[0][0] + e * ND, R);
-      }
+        const int slot = ent[4 * e + 2] >> kBatchOffsetBits;
+        line_work_face<K, D, RP>(W.tab, a, info, hd.x, slot, L, &W.U[0][0] + e * ND, &W.NB[0][0] + e * ND, W.REC,
+                                 t);
+      } else {
 #pragma unroll
-      for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = R[c];
-      sync();
+        for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
+      }
+      wave_sync();
       const int r1 = min(total, base + NT);
 #pragma unroll
       for (int e = 0; e < ME; ++e) {
@@ -1502,17 +1572,17 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
               const T* R0 = W.REC + (FS::D0 + il) * RP;
               const T* Rn = W.REC + (FS::DN + il) * RP;
               T s = 0;
-#pragma unroll 1
-              for (int r = rlo; r < rhi; ++r) {
-                const T w = en * R0[r] + den * Rn[r];
-                s += D == 3 ? Rv[r] * w : w;
+#pragma unroll 2
+              for (int rr = rlo; rr < rhi; ++rr) {
+                const T w = en * R0[rr] + den * Rn[rr];
+                s += D == 3 ? Rv[rr] * w : w;
               }
               acc[e][j] += s;
             }
           }
         }
       }
-      sync();
+      wave_sync();
     }
     batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
   }
@@ -1827,40 +1897,41 @@ struct DkBatchWork {
   T Yo[ME][ND];
   T Wn[FACE ? ME : 1][FACE ? ND : 1];
   T Yn[FACE ? ME : 1][FACE ? ND : 1];
-  int ent[ME][4];
+  int rec[batch_record_ints(ME)];
 };
 
 template <int K, int D, typename T, bool FACE>
 __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __restrict__ w, const T* __restrict__ u,
-                                                    T* __restrict__ dk, const int32_t* __restrict__ batches,
-                                                    const int32_t* __restrict__ entries,
-                                                    const int32_t* __restrict__ lines, int n_batches) {
+                                                    T* __restrict__ dk, const int32_t* __restrict__ brec,
+                                                    const int32_t* __restrict__ desc, int n_batches) {
   using BW = DkBatchWork<K, D, T, FACE>;
-  constexpr int ND = BW::ND, ME = BW::ME, NT = 64;
+  constexpr int ND = BW::ND, ME = BW::ME, NT = 64, NR = batch_record_ints(ME);
   __shared__ BW W;
   for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   const int t = threadIdx.x;
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
-    const int e0 = batches[4 * b], ne = batches[4 * b + 1], total = batches[4 * b + 2], l0 = batches[4 * b + 3];
-    if (t < 4 * ne) (&W.ent[0][0])[t] = entries[4 * e0 + t];
+    if (t < NR) W.rec[t] = brec[(int64_t)b * NR + t];
     sync();
+    const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
+    const int* ent = W.rec + 4;
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
-      const int64_t ro = (int64_t)W.ent[e][0] * ND + l;
+      const int64_t ro = (int64_t)ent[4 * e] * ND + l;
       W.Wo[e][l] = w[ro];
       W.Yo[e][l] = u[ro];
       if constexpr (FACE) {
-        const int64_t rn = (int64_t)W.ent[e][3] * ND + l;
+        const int64_t rn = (int64_t)ent[4 * e + 3] * ND + l;
         W.Wn[e][l] = w[rn];
         W.Yn[e][l] = u[rn];
       }
     }
     sync();
     for (int g = t; g < total; g += NT) {
-      const int2 hd = *reinterpret_cast<const int2*>(lines + 2 * (l0 + g));
+      const int2 hd = g < kBatchLines ? *reinterpret_cast<const int2*>(desc + 2 * ((int64_t)b * kBatchLines + g))
+                                      : batch_desc(desc, n_batches, ovf, g);
       const int info = hd.y & 0xffffff, e = hd.y >> 24;
       int ax = (info >> 16) & 0xf;
-      const int s = W.ent[e][2] >> kBatchOffsetBits;
+      const int s = ent[4 * e + 2] >> kBatchOffsetBits;
       if constexpr (FACE) {
         const int nax = s >> 1;
         ax = ax < nax ? ax : ax + 1;
@@ -1873,6 +1944,14 @@ __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __res
     }
     sync();
   }
+}
+
+// resident workgroups of a kernel per compute unit (persistent grids)
+template <typename Kern>
+int blocks_per_cu(Kern kernel) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 64, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
 }
 
 template <int K, int D, typename T>
@@ -1894,11 +1973,11 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       if (a.n_sfaces > 0)
         face_dk_kernel<K, D, T><<<(int)std::min<int64_t>((a.n_sfaces + CF - 1) / CF, 1 << 20), 64, 0, s>>>(a, x, y, dk);
       if (a.n_vbatch > 0)
-        cut_dk_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.vbatch, a.ventry,
-                                                                                   a.vline, a.n_vbatch);
+        cut_dk_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.vbrec, a.vdesc,
+                                                                                   a.n_vbatch);
       if (a.n_fbatch > 0)
-        cut_dk_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.fbatch, a.fentry,
-                                                                                  a.fline, a.n_fbatch);
+        cut_dk_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.fbrec, a.fdesc,
+                                                                                  a.n_fbatch);
     }
     return hipGetLastError();
   }
@@ -1920,12 +1999,16 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
         constexpr int CW = KronShape<K, D>::C;
         const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
         if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
-        if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0)
-          cut_batch_kernel<K, D, T><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.vbatch, a.ventry,
-                                                                                        a.vline, a.n_vbatch);
-        if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0)
-          cut_face_kernel<K, D, T><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, v, a.fbatch, a.fentry,
-                                                                                       a.fline, a.n_fbatch);
+        if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
+          static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
+          const int g = std::min(a.n_vbatch, nb * a.n_cu);
+          cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);
+        }
+        if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0) {
+          static const int nb = blocks_per_cu(cut_face_kernel<K, D, T>);
+          const int g = std::min(a.n_fbatch, nb * a.n_cu);
+          cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
+        }
       }
     } else {
       if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
