@@ -43,13 +43,16 @@ struct Shape {
 
 __device__ __forceinline__ void sync() { __syncthreads(); }
 
-// Workgroups of exactly one wavefront: the LDS operations of a wavefront are
-// performed in issue order, so only the compiler has to be kept from moving
-// memory accesses across this point (no s_barrier, and no wait for
-// outstanding global loads, which may stay in flight).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_wave_barrier();
-  asm volatile("" ::: "memory");
+// Workgroups are handed to the 8 XCDs round robin, each XCD with its own L2.
+// xcd_block renumbers them so that each XCD works on one contiguous range of
+// block indices (a contiguous range of cells), which keeps the neighbours a
+// cell reads in the L2 that read them first.  A bijection of [0, gridDim.x).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  if (nb < kXcds) return b;
+  const int q = nb / kXcds, r = nb % kXcds, x = b % kXcds, i = b / kXcds;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
 // out = M (or M^T) applied along axis AX of a K^N tensor
@@ -694,14 +697,52 @@ struct KronShape {
   static constexpr int NT = 64;
 };
 
+// LDS layout of a cell tensor in the Kronecker kernel: element (i0, i1, i2)
+// at ((i0 + i2) mod K) + K ((i1 + i2) mod K) + K^2 i2 (3D), (i0 + i1) mod K +
+// K i1 (2D).  The lanes of a cell (one per line) then hit distinct banks in
+// the passes along every axis, and the cell stride (NDP, = 16 mod 32
+// elements) separates the cells of a wave.
+template <int K, int D>
+struct KronLayout {
+  static constexpr int ND = ipow(K, D);
+  static constexpr int NDP = ND + (16 - ND % 32 + 32) % 32;
+  static __device__ __forceinline__ int at(int i0, int i1, int i2) {
+    if constexpr (D == 3) return (i0 + i2) % K + K * ((i1 + i2) % K) + K * K * i2;
+    else return (i0 + i1) % K + K * i1;
+  }
+  // the K LDS positions of line l along axis AX
+  template <int AX>
+  static __device__ __forceinline__ void line(int l, int* pos) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      if constexpr (D == 2) pos[q] = AX == 0 ? at(q, l, 0) : at(l, q, 0);
+      else {
+        const int a = l % K, b = l / K;
+        pos[q] = AX == 0 ? at(q, a, b) : (AX == 1 ? at(a, q, b) : at(a, b, q));
+      }
+    }
+  }
+};
+
 template <int K, int D, typename T>
 struct KronWork {
-  static constexpr int ND = KronShape<K, D>::ND, C = KronShape<K, D>::C;
-  T A[C][ND];
-  T B[C][ND];
-  T Cc[C][ND];
-  T U[C][ND];
+  static constexpr int NDP = KronLayout<K, D>::NDP, C = KronShape<K, D>::C;
+  T A[C][NDP];
+  T B[C][NDP];
+  T Cc[C][NDP];
+  T U[C][NDP];
 };
+
+template <int K, typename T>
+__device__ __forceinline__ void kl_load(const T* arr, const int* pos, T* v) {
+#pragma unroll
+  for (int q = 0; q < K; ++q) v[q] = arr[pos[q]];
+}
+template <int K, typename T>
+__device__ __forceinline__ void kl_store(T* arr, const int* pos, const T* v) {
+#pragma unroll
+  for (int q = 0; q < K; ++q) arr[pos[q]] = v[q];
+}
 
 // element stride of the lines along axis ax, and the first element of line l
 template <int K, int D, int AX>
@@ -810,7 +851,7 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
   const int c = lane / NL, l = lane % NL;
   const bool active = c < C;
   const bool vol = with_volume && (a.terms & 1) != 0;
-  for (int c0 = blockIdx.x * C; c0 < n_list; c0 += gridDim.x * C) {
+  for (int c0 = xcd_block() * C; c0 < n_list; c0 += gridDim.x * C) {
     const int ci = c0 + c;
     const bool valid = active && ci < n_list;
     const int r = valid ? list[ci] : 0;
@@ -837,71 +878,75 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
     T* B = W.B[active ? c : 0];
     T* Cc = W.Cc[active ? c : 0];
     T t0[K], t1[K], t2[K];
+    int px[K], py[K], pz[K];
+    KronLayout<K, D>::template line<0>(l, px);
+    KronLayout<K, D>::template line<1>(l, py);
+    if constexpr (D == 3) KronLayout<K, D>::template line<2>(l, pz);
     // pass x1: R_x = KS u + x-faces -> A ; u -> U
     if (valid) {
-      lds_line_store<K, D, 0>(U, bx, ux);
+      kl_store<K>(U, px, ux);
       if (vol) line_mat<K>(KS, ux, t0);
       else {
 #pragma unroll
         for (int q = 0; q < K; ++q) t0[q] = 0;
       }
       line_faces<K>(tab, a, fl, 0, ux, nb[0], nb[1], t0);
-      lds_line_store<K, D, 0>(A, bx, t0);
+      kl_store<K>(A, px, t0);
     }
     sync();
     if constexpr (D == 3) {
       // pass y1: R_y = KS u + y-faces -> Cc ; P = M_y R_x -> B
       if (valid) {
-        lds_line_load<K, D, 1>(U, by, t1);
+        kl_load<K>(U, py, t1);
         if (vol) line_mat<K>(KS, t1, t0);
         else {
 #pragma unroll
           for (int q = 0; q < K; ++q) t0[q] = 0;
         }
         line_faces<K>(tab, a, fl, 1, t1, nb[2], nb[3], t0);
-        lds_line_store<K, D, 1>(Cc, by, t0);
-        lds_line_load<K, D, 1>(A, by, t1);
+        kl_store<K>(Cc, py, t0);
+        kl_load<K>(A, py, t1);
         line_mat<K>(M, t1, t2);
-        lds_line_store<K, D, 1>(B, by, t2);
+        kl_store<K>(B, py, t2);
       }
       sync();
       // pass x2: S = P + M_x R_y -> A
       if (valid) {
-        lds_line_load<K, D, 0>(Cc, bx, t1);
+        kl_load<K>(Cc, px, t1);
         line_mat<K>(M, t1, t2);
-        lds_line_load<K, D, 0>(B, bx, t1);
+        kl_load<K>(B, px, t1);
 #pragma unroll
         for (int q = 0; q < K; ++q) t2[q] += t1[q];
-        lds_line_store<K, D, 0>(A, bx, t2);
+        kl_store<K>(A, px, t2);
       }
       sync();
       // pass z1: R_z = KS u + z-faces -> Cc ; O = M_z S -> B
       if (valid) {
-        lds_line_load<K, D, 2>(U, bz, t1);
+        kl_load<K>(U, pz, t1);
         if (vol) line_mat<K>(KS, t1, t0);
         else {
 #pragma unroll
           for (int q = 0; q < K; ++q) t0[q] = 0;
         }
         line_faces<K>(tab, a, fl, 2, t1, nb[4], nb[5], t0);
-        lds_line_store<K, D, 2>(Cc, bz, t0);
-        lds_line_load<K, D, 2>(A, bz, t1);
+        kl_store<K>(Cc, pz, t0);
+        kl_load<K>(A, pz, t1);
         line_mat<K>(M, t1, t2);
-        lds_line_store<K, D, 2>(B, bz, t2);
+        kl_store<K>(B, pz, t2);
       }
       sync();
       // pass x3: V = M_x R_z -> A
       if (valid) {
-        lds_line_load<K, D, 0>(Cc, bx, t1);
+        kl_load<K>(Cc, px, t1);
         line_mat<K>(M, t1, t2);
-        lds_line_store<K, D, 0>(A, bx, t2);
+        kl_store<K>(A, px, t2);
       }
       sync();
       // pass y2: v = hs (M_y V + O)
       if (valid) {
-        lds_line_load<K, D, 1>(A, by, t1);
+        kl_load<K>(A, py, t1);
         line_mat<K>(M, t1, t2);
-        lds_line_load<K, D, 1>(B, by, t1);
+        kl_load<K>(B, py, t1);
         T* out = v + (int64_t)r * ND;
 #pragma unroll
         for (int q = 0; q < K; ++q) out[by + q * K] = a.hs * (t2[q] + t1[q]);
@@ -909,24 +954,24 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
     } else {
       // pass y1: R_y = KS u + y-faces -> Cc ; P = M_y R_x -> B
       if (valid) {
-        lds_line_load<K, D, 1>(U, by, t1);
+        kl_load<K>(U, py, t1);
         if (vol) line_mat<K>(KS, t1, t0);
         else {
 #pragma unroll
           for (int q = 0; q < K; ++q) t0[q] = 0;
         }
         line_faces<K>(tab, a, fl, 1, t1, nb[2], nb[3], t0);
-        lds_line_store<K, D, 1>(Cc, by, t0);
-        lds_line_load<K, D, 1>(A, by, t1);
+        kl_store<K>(Cc, py, t0);
+        kl_load<K>(A, py, t1);
         line_mat<K>(M, t1, t2);
-        lds_line_store<K, D, 1>(B, by, t2);
+        kl_store<K>(B, py, t2);
       }
       sync();
       // pass x2: v = hs (P + M_x R_y)
       if (valid) {
-        lds_line_load<K, D, 0>(Cc, bx, t1);
+        kl_load<K>(Cc, px, t1);
         line_mat<K>(M, t1, t2);
-        lds_line_load<K, D, 0>(B, bx, t1);
+        kl_load<K>(B, px, t1);
         T* out = v + (int64_t)r * ND;
 #pragma unroll
         for (int q = 0; q < K; ++q) out[bx + q] = a.hs * (t2[q] + t1[q]);
@@ -1279,7 +1324,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     const BatchFetch cur = nxt;
     if (t < NR) W.rec[t] = cur.rec;
-    wave_sync();
+    sync();
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
     const int* ent = W.rec + 4;
@@ -1302,7 +1347,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
     }
     T acc[ME][NPL];
     batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
-    wave_sync();
+    sync();
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
       bool done = false;
@@ -1326,7 +1371,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
 #pragma unroll
         for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
       }
-      wave_sync();
+      sync();
       const int r1 = min(total, base + NT);
 #pragma unroll
       for (int e = 0; e < ME; ++e) {
@@ -1337,7 +1382,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
           if constexpr (D == 3) reduce_axis<K, D, 2, NPL>(W.REC, max(a2, base) - base, min(a3, r1) - base, dof_i, acc[e]);
         }
       }
-      wave_sync();
+      sync();
     }
     batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
   }
@@ -1503,7 +1548,7 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     const BatchFetch cur = nxt;
     if (t < NR) W.rec[t] = cur.rec;
-    wave_sync();
+    sync();
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
     const int* ent = W.rec + 4;
@@ -1532,7 +1577,7 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
     }
     T acc[ME][NPL];
     batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
-    wave_sync();
+    sync();
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
       if (g < total) {
@@ -1548,7 +1593,7 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
 #pragma unroll
         for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
       }
-      wave_sync();
+      sync();
       const int r1 = min(total, base + NT);
 #pragma unroll
       for (int e = 0; e < ME; ++e) {
@@ -1582,7 +1627,7 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
           }
         }
       }
-      wave_sync();
+      sync();
     }
     batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
   }
