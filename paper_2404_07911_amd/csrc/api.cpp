@@ -458,9 +458,10 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     bool batch_overflow = false;
     auto make_batches = [&](bool face, std::vector<int32_t>& brec, std::vector<int32_t>& desc, int32_t& n_batches) {
       const int me = ufem::batch_max_entries((int)P.nd(), face);
+      const int mc = ufem::batch_max_cells((int)P.nd(), face);
       const int nr = ufem::batch_record_ints(me);
       std::vector<int32_t> rec, lines, ovf;  // current batch; overflow area
-      int cur_n = 0;
+      int cur_n = 0, cur_cells = 0;
       std::vector<int32_t> slots;            // first-round descriptors of all batches
       auto close = [&]() {
         if (cur_n == 0) return;
@@ -476,6 +477,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         }
         if (total > ufem::kBatchLines) ovf.insert(ovf.end(), lines.begin() + 2 * ufem::kBatchLines, lines.end());
         cur_n = 0;
+        cur_cells = 0;
         lines.clear();
       };
       for (int32_t ci : order) {
@@ -498,7 +500,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
           if (face && ce[4 * e + 3] < 0) batch_overflow = true;  // a cut face always has a neighbour
         }
         const int cur_lines = (int)lines.size() / 2;
-        if (cur_n > 0 && (cur_lines + nl > ufem::kBatchLines || cur_n + n_e > me)) close();
+        if (cur_n > 0 && (cur_lines + nl > ufem::kBatchLines || cur_n + n_e > me || cur_cells + 1 > mc)) close();
         if (batch_overflow || n_e > me || nl >= (1 << ufem::kBatchOffsetBits)) {
           batch_overflow = true;
           return;
@@ -528,6 +530,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
           en[3] = ce[4 * e + 3];
         }
         cur_n += n_e;
+        ++cur_cells;
         if ((int)lines.size() / 2 >= ufem::kBatchLines) close();
       }
       close();

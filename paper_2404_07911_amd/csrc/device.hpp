@@ -38,7 +38,13 @@ constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
 // volume / interface entries (slot 15), in-face axes for cut-face entries
 // (one per cut face of a cut cell).  Entries of one cell are consecutive and
 // in one batch.
-constexpr __host__ __device__ int batch_max_entries(int, bool face) { return face ? 12 : 8; }
+// entries (one per cell, or per cut face of a cell) and cells of a batch
+constexpr __host__ __device__ int batch_max_entries(int nd, bool face) {
+  return face ? (nd <= 64 ? 12 : 6) : (nd <= 64 ? 8 : (nd <= 125 ? 4 : 1));
+}
+constexpr __host__ __device__ int batch_max_cells(int nd, bool face) {
+  return face ? (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1)) : batch_max_entries(nd, false);
+}
 constexpr __host__ __device__ int batch_record_ints(int me) { return 4 + 4 * me; }
 constexpr int kBatchLines = 64;        // lines per round (one per lane)
 constexpr int kBatchOffsetBits = 24;   // bits of the in-batch line offset

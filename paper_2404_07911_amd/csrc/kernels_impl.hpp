@@ -1390,17 +1390,16 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
 
 // ---- cut-face lines
 // Each entry is one cut face of a cut cell (slot s = 2 N + side, N the
-// normal axis).  The DoFs of the cell and of the neighbour across the face
-// are staged transposed to (normal axis, in-face axis A, in-face axis B),
-// A < B the other cell axes, so that one code path serves lines along A and
-// along B: the columns along the line contract the normal axis with the
-// tabulated end-point values (and first derivatives) of either side and the
-// other in-face axis with the Lagrange values of the line's coordinate.
-// The SIPG flux needs the value and the normal derivative of both traces
-// only, and the line record is [VF | D0 | DN] (3D) or [D0 | DN] (2D): the
+// normal axis).  Only the traces enter the SIPG flux: in the batch prologue
+// the value and the normal derivative of both sides are formed on the face's
+// K^(D-1) node grid (in-face axes A < B, the other cell axes; the normal-axis
+// contraction with the tabulated end-point values E, E' of either side).  A
+// line along A or B then contracts the other in-face axis with the Lagrange
+// values of its coordinate (one code path for both), evaluates at its
+// points, and leaves the record [VF | D0 | DN] (3D) or [D0 | DN] (2D): the
 // test-function coefficient of DoF (i_line, i_N, i_F) is
 // VF[i_F] (E[i_N] D0[i_line] + E'[i_N] DN[i_line]) with E the own side's
-// end-point values.
+// end-point values.  Sums are kept per cell (up to batch_max_cells cells).
 template <int K, int D>
 struct FaceShape {
   static constexpr int NF = ipow(K, D - 1);
@@ -1410,11 +1409,10 @@ struct FaceShape {
 
 template <int K, int D, typename T>
 struct FaceWork {
-  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), true),
+  static constexpr int NF = FaceShape<K, D>::NF, ME = batch_max_entries(ipow(K, D), true),
                        RS = FaceShape<K, D>::RS, RP = BatchShape<K, D>::RP;
   T tab[TabOff::size(K)];
-  T U[ME][ND];  // transposed: U[e][iN * K^(D-1) + iA * K^(D-2) + iB]
-  T NB[ME][ND];
+  T TR[ME][4][NF];  // own value, own normal derivative, neighbour value, neighbour normal derivative
   T REC[RS * RP];
   int rec[batch_record_ints(ME)];
 };
@@ -1440,20 +1438,17 @@ __device__ __forceinline__ void line_load_face(const DevArgs<T>& a, int info, in
   }
 }
 
-// one cut-face line, along in-face axis A (alongB false) or B
+// one cut-face line, along in-face axis A (alongB false) or B; TR: the
+// entry's traces
 template <int K, int D, int RP, typename T>
 __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a, int info, int p0, int slot,
-                                               LinePts<T>& L, const T* Uo, const T* Un, T* REC, int r) {
+                                               LinePts<T>& L, const T (*TR)[FaceShape<K, D>::NF], T* REC, int r) {
   using FS = FaceShape<K, D>;
-  constexpr int NF = FS::NF;
   const T* Xn = tab + TabOff::X(K);
   const T* ID = tab + TabOff::ID(K);
   const int n = info & 0xffff;
   const bool alongB = ((info >> 16) & 0xf) == 1;
-  const int side = slot & 1;
-  const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-  const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-  const T sigma = side ? T(1) : T(-1);
+  const T sigma = (slot & 1) ? T(1) : T(-1);
   T F[K], dF[K];
   if constexpr (D == 3) {
     lagrange1d<K>(Xn, ID, L.t1, F, dF);
@@ -1468,24 +1463,13 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
     T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
 #pragma unroll
     for (int f = 0; f < (D == 3 ? K : 1); ++f) {
-      // offset of (lk, f) within a normal layer: along A the line index is
-      // the A index (stride K), along B the B index (stride 1)
+      // along A the line index is the A index (stride K), along B the B index
       const int o = D == 3 ? (alongB ? lk + f * K : lk * K + f) : lk;
-      T s0 = 0, s1 = 0, r0 = 0, r1 = 0;
-#pragma unroll
-      for (int nn = 0; nn < K; ++nn) {
-        const T uo = Uo[nn * NF + o], un = Un[nn * NF + o];
-        s0 += Eo[nn] * uo;
-        s1 += Eo[K + nn] * uo;
-        r0 += En[nn] * un;
-        r1 += En[K + nn] * un;
-      }
-      a0 += F[f] * s0;
-      a1 += F[f] * s1;
-      b0 += F[f] * r0;
-      b1 += F[f] * r1;
+      a0 += F[f] * TR[0][o];
+      a1 += F[f] * TR[1][o];
+      b0 += F[f] * TR[2][o];
+      b1 += F[f] * TR[3][o];
     }
-    asm volatile("" : "+v"(a0), "+v"(a1), "+v"(b0), "+v"(b1)::"memory");
     c0[lk] = a0;
     cn[lk] = a1;
     m0[lk] = b0;
@@ -1536,8 +1520,9 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
                                                       const int32_t* __restrict__ desc, int n_batches) {
   using FW = FaceWork<K, D, T>;
   using FS = FaceShape<K, D>;
-  constexpr int ND = FW::ND, ME = FW::ME, RS = FW::RS, RP = FW::RP, NT = BatchShape<K, D>::NT,
-                NPL = BatchShape<K, D>::NPL, NF = FS::NF, NR = batch_record_ints(ME);
+  constexpr int ND = BatchShape<K, D>::ND, ME = FW::ME, RS = FW::RS, RP = FW::RP, NT = BatchShape<K, D>::NT,
+                NPL = BatchShape<K, D>::NPL, NF = FS::NF, NR = batch_record_ints(ME),
+                MC = batch_max_cells(ipow(K, D), true);
   constexpr int OFS = (1 << kBatchOffsetBits) - 1;
   __shared__ FW W;
   const int t = threadIdx.x;
@@ -1552,31 +1537,66 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
     const int* ent = W.rec + 4;
-    int rank[ME], ofs[ME + 1], nA[ME], slt[ME];
-#pragma unroll
-    for (int e = 0; e < ME; ++e) {
-      rank[e] = e < ne ? ent[4 * e] : -1;
-      ofs[e] = e < ne ? (ent[4 * e + 2] & OFS) : total;
-      nA[e] = ent[4 * e + 1] & 0xffff;
-      slt[e] = ent[4 * e + 2] >> kBatchOffsetBits;
-    }
-    ofs[ME] = total;
     int2 hd = cur.hd;
     LinePts<T> L;
     if (t < total) line_load_face<D>(a, hd.y & 0xffffff, hd.x, 0, L);
-    // stage the DoFs of cell and neighbour, transposed to (N, A, B)
-    for (int idx = t; idx < ne * ND; idx += NT) {
-      const int e = idx / ND, l = idx % ND;
-      const int N = (ent[4 * e + 2] >> kBatchOffsetBits) >> 1;
-      const int d0 = l % K, d1 = (l / K) % K, d2 = D == 3 ? l / (K * K) : 0;
-      int tr;
-      if constexpr (D == 3) tr = N == 0 ? d0 * NF + d1 * K + d2 : (N == 1 ? d1 * NF + d0 * K + d2 : d2 * NF + d0 * K + d1);
-      else tr = N == 0 ? d0 * K + d1 : d1 * K + d0;
-      W.U[e][tr] = x[(int64_t)ent[4 * e] * ND + l];
-      W.NB[e][tr] = x[(int64_t)ent[4 * e + 3] * ND + l];
+    // traces of cell and neighbour on the face node grid (A, B)
+    for (int idx = t; idx < ne * NF; idx += NT) {
+      const int e = idx / NF, o = idx % NF;
+      const int sl = ent[4 * e + 2] >> kBatchOffsetBits, N = sl >> 1;
+      const int ia = o / (D == 3 ? K : 1), ib = D == 3 ? o % K : 0;
+      // physical stride of the normal axis and offset of the in-face node
+      int sN, off;
+      if constexpr (D == 3) {
+        sN = N == 0 ? 1 : (N == 1 ? K : K * K);
+        off = N == 0 ? ia * K + ib * K * K : (N == 1 ? ia + ib * K * K : ia + ib * K);
+      } else {
+        sN = N == 0 ? 1 : K;
+        off = N == 0 ? ia * K : ia;
+      }
+      const T* Eo = W.tab + ((sl & 1) ? TabOff::E1(K) : TabOff::E0(K));
+      const T* En = W.tab + ((sl & 1) ? TabOff::E0(K) : TabOff::E1(K));
+      const T* uo = x + (int64_t)ent[4 * e] * ND + off;
+      const T* un = x + (int64_t)ent[4 * e + 3] * ND + off;
+      T o0 = 0, o1 = 0, n0 = 0, n1 = 0;
+#pragma unroll
+      for (int nn = 0; nn < K; ++nn) {
+        const T a0 = uo[nn * sN], b0 = un[nn * sN];
+        o0 += Eo[nn] * a0;
+        o1 += Eo[K + nn] * a0;
+        n0 += En[nn] * b0;
+        n1 += En[K + nn] * b0;
+      }
+      W.TR[e][0][o] = o0;
+      W.TR[e][1][o] = o1;
+      W.TR[e][2][o] = n0;
+      W.TR[e][3][o] = n1;
     }
-    T acc[ME][NPL];
-    batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
+    // per-cell sums of the lane's DoFs, starting from v's rows
+    int crank[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) crank[c] = -1;
+    {
+      int c = -1, prev = -1;
+      for (int e = 0; e < ne; ++e) {
+        const int r = ent[4 * e];
+        if (r != prev) {
+          ++c;
+          prev = r;
+#pragma unroll
+          for (int cc = 0; cc < MC; ++cc)
+            if (cc == c) crank[cc] = r;
+        }
+      }
+    }
+    T acc[MC][NPL];
+#pragma unroll
+    for (int c = 0; c < MC; ++c)
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        const int l = t + NT * j;
+        acc[c][j] = (crank[c] >= 0 && l < ND) ? v[(int64_t)crank[c] * ND + l] : T(0);
+      }
     sync();
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
@@ -1587,49 +1607,67 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
         }
         const int info = hd.y & 0xffffff, e = hd.y >> 24;
         const int slot = ent[4 * e + 2] >> kBatchOffsetBits;
-        line_work_face<K, D, RP>(W.tab, a, info, hd.x, slot, L, &W.U[0][0] + e * ND, &W.NB[0][0] + e * ND, W.REC,
-                                 t);
+        line_work_face<K, D, RP>(W.tab, a, info, hd.x, slot, L, W.TR[e], W.REC, t);
       } else {
 #pragma unroll
         for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
       }
       sync();
       const int r1 = min(total, base + NT);
+      int c = -1, prev = -1;
+      for (int e = 0; e < ne; ++e) {
+        const int rank = ent[4 * e];
+        if (rank != prev) {
+          ++c;
+          prev = rank;
+        }
+        const int lo0 = ent[4 * e + 2] & OFS;
+        const int hi1 = e + 1 < ne ? (ent[4 * (e + 1) + 2] & OFS) : total;
+        if (lo0 >= r1 || hi1 <= base) continue;
+        const int sl = ent[4 * e + 2] >> kBatchOffsetBits, N = sl >> 1;
+        const int nA = ent[4 * e + 1] & 0xffff;
+        const int A = N == 0 ? 1 : 0, B = N == 2 ? 1 : 2;
+        const T* E = W.tab + ((sl & 1) ? TabOff::E1(K) : TabOff::E0(K));
+        T s[NPL];
 #pragma unroll
-      for (int e = 0; e < ME; ++e) {
-        if (e < ne && ofs[e] < r1 && ofs[e + 1] > base) {
-          const int N = slt[e] >> 1;
-          const int A = N == 0 ? 1 : 0, B = N == 2 ? 1 : 2;
-          const T* E = W.tab + ((slt[e] & 1) ? TabOff::E1(K) : TabOff::E0(K));
+        for (int j = 0; j < NPL; ++j) s[j] = 0;
 #pragma unroll
-          for (int grp = 0; grp < (D == 3 ? 2 : 1); ++grp) {
-            const int lo = grp == 0 ? ofs[e] : ofs[e] + nA[e];
-            const int hi = grp == 0 ? ofs[e] + nA[e] : ofs[e + 1];
-            const int rlo = max(lo, base) - base, rhi = min(hi, r1) - base;
-            if (rlo >= rhi) continue;
-            const int LA = grp == 0 ? A : B, FA = grp == 0 ? B : A;
+        for (int grp = 0; grp < (D == 3 ? 2 : 1); ++grp) {
+          const int lo = grp == 0 ? lo0 : lo0 + nA;
+          const int hi = grp == 0 ? lo0 + nA : hi1;
+          const int rlo = max(lo, base) - base, rhi = min(hi, r1) - base;
+          if (rlo >= rhi) continue;
+          const int LA = grp == 0 ? A : B, FA = grp == 0 ? B : A;
 #pragma unroll
-            for (int j = 0; j < NPL; ++j) {
-              auto pick = [&](int ax) { return ax == 0 ? dof_i[j][0] : (ax == 1 ? dof_i[j][1] : dof_i[j][2]); };
-              const int iN = pick(N), il = pick(LA), iF = pick(FA);
-              const T en = E[iN], den = E[K + iN];
-              const T* Rv = W.REC + (FS::VF + iF) * RP;
-              const T* R0 = W.REC + (FS::D0 + il) * RP;
-              const T* Rn = W.REC + (FS::DN + il) * RP;
-              T s = 0;
+          for (int j = 0; j < NPL; ++j) {
+            auto pick = [&](int ax) { return ax == 0 ? dof_i[j][0] : (ax == 1 ? dof_i[j][1] : dof_i[j][2]); };
+            const int iN = pick(N), il = pick(LA), iF = pick(FA);
+            const T en = E[iN], den = E[K + iN];
+            const T* Rv = W.REC + (FS::VF + iF) * RP;
+            const T* R0 = W.REC + (FS::D0 + il) * RP;
+            const T* Rn = W.REC + (FS::DN + il) * RP;
 #pragma unroll 2
-              for (int rr = rlo; rr < rhi; ++rr) {
-                const T w = en * R0[rr] + den * Rn[rr];
-                s += D == 3 ? Rv[rr] * w : w;
-              }
-              acc[e][j] += s;
+            for (int rr = rlo; rr < rhi; ++rr) {
+              const T w = en * R0[rr] + den * Rn[rr];
+              s[j] += D == 3 ? Rv[rr] * w : w;
             }
           }
         }
+#pragma unroll
+        for (int cc = 0; cc < MC; ++cc)
+          if (cc == c)
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) acc[cc][j] += s[j];
       }
       sync();
     }
-    batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
+#pragma unroll
+    for (int c = 0; c < MC; ++c)
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        const int l = t + NT * j;
+        if (crank[c] >= 0 && l < ND) v[(int64_t)crank[c] * ND + l] = acc[c][j];
+      }
   }
 }
 
@@ -2027,8 +2065,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     return hipGetLastError();
   }
   if (!adj) {
-    bool fast_cut = false;
-    if constexpr (ipow(K, D) <= 125) fast_cut = a.kappa == nullptr;
+    const bool fast_cut = a.kappa == nullptr;
     if (a.kappa == nullptr) {
       constexpr int CW = KronShape<K, D>::C;
       const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
@@ -2037,23 +2074,21 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
     }
     if (fast_cut) {
-      if constexpr (ipow(K, D) <= 125) {
-        // structured faces and ghost penalty of the cut cells (overwrites
-        // their rows), then the volume / interface lines and the cut-face
-        // lines are added
-        constexpr int CW = KronShape<K, D>::C;
-        const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
-        if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
-        if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
-          static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
-          const int g = std::min(a.n_vbatch, nb * a.n_cu);
-          cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);
-        }
-        if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0) {
-          static const int nb = blocks_per_cu(cut_face_kernel<K, D, T>);
-          const int g = std::min(a.n_fbatch, nb * a.n_cu);
-          cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
-        }
+      // structured faces and ghost penalty of the cut cells (overwrites
+      // their rows), then the volume / interface lines and the cut-face
+      // lines are added
+      constexpr int CW = KronShape<K, D>::C;
+      const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
+      if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
+      if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
+        static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
+        const int g = std::min(a.n_vbatch, nb * a.n_cu);
+        cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);
+      }
+      if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0) {
+        static const int nb = blocks_per_cu(cut_face_kernel<K, D, T>);
+        const int g = std::min(a.n_fbatch, nb * a.n_cu);
+        cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
       }
     } else {
       if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);

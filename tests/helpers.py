@@ -51,6 +51,10 @@ SMALL_CASES = {
     "ball3d_p4": (ui.ball3d, dict(seed=3, n=8, degree=4)),
     "balls3d_p2": (ui.balls3d, dict(seed=0, n=16, degree=2, n_balls=5)),
     "balls3d_p3": (ui.balls3d, dict(seed=4, n=12, degree=3, n_balls=3)),
+    "ball3d_p5": (ui.ball3d, dict(seed=5, n=5, degree=5)),
+    "ball3d_p6": (ui.ball3d, dict(seed=6, n=5, degree=6)),
+    "ball3d_p7": (ui.ball3d, dict(seed=7, n=5, degree=7)),
+    "disk2d_p7": (ui.disk2d, dict(seed=7, n=8, degree=7)),
 }
 
 
