@@ -1266,23 +1266,29 @@ __device__ __forceinline__ int2 batch_desc(const int32_t* __restrict__ desc, int
 }
 
 // ---- volume and interface lines
+// Every entry of a volume batch is one cut cell.  In 3D the records of a
+// round are reduced by groups of K^2 lanes, lane (i1, ik) of a group forming
+// P = V1[i1] D0[ik] + dV1[i1] D1[ik] and Q = V1[i1] D2[ik] for one record and
+// adding V2[i2] P + dV2[i2] Q to its K DoFs (ik, i1, i2), i2 = 0..K-1; the
+// 64 / K^2 groups take every G-th record and are added into the cell's LDS
+// row with LDS atomics.  (2D: one lane per DoF.)
 template <int K, int D, typename T>
 struct BatchWork {
   static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false),
                        RS = LineShape<K, D>::RS, RP = BatchShape<K, D>::RP;
   T tab[TabOff::size(K)];
   T U[ME][ND];
+  T OUT[ME][ND];
   T REC[RS * RP];  // component c of the round's record r at REC[c * RP + r]
   int rec[batch_record_ints(ME)];
 };
 
-// acc += the records [lo, hi) of the round, all along axis KA
-template <int K, int D, int KA, int NPL, typename T>
-__device__ __forceinline__ void reduce_axis(const T* REC, int lo, int hi, const int (*dof_i)[3], T* acc) {
-  using LS = LineShape<K, D>;
-  constexpr int P = BatchShape<K, D>::RP;
+// 2D: acc += the records [lo, hi) of the round, all along axis KA
+template <int K, int KA, int NPL, typename T>
+__device__ __forceinline__ void reduce_axis_2d(const T* REC, int lo, int hi, const int (*dof_i)[3], T* acc) {
+  using LS = LineShape<K, 2>;
+  constexpr int P = BatchShape<K, 2>::RP;
   constexpr int O1 = KA == 0 ? 1 : 0;
-  constexpr int O2 = KA == 2 ? 1 : 2;
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
     const int ik = dof_i[j][KA], i1 = dof_i[j][O1];
@@ -1291,18 +1297,40 @@ __device__ __forceinline__ void reduce_axis(const T* REC, int lo, int hi, const 
     const T* Rd0 = REC + (LS::D0 + ik) * P;
     const T* Rd1 = REC + (LS::D1 + ik) * P;
     T s = 0;
-    if constexpr (D == 3) {
-      const int i2 = dof_i[j][O2];
-      const T* Rv2 = REC + (LS::V2 + i2) * P;
-      const T* Rdv2 = REC + (LS::DV2 + i2) * P;
-      const T* Rd2 = REC + (LS::D2 + ik) * P;
 #pragma unroll 2
-      for (int r = lo; r < hi; ++r) s += Rv2[r] * (Rv1[r] * Rd0[r] + Rdv1[r] * Rd1[r]) + Rv1[r] * Rdv2[r] * Rd2[r];
-    } else {
-#pragma unroll 2
-      for (int r = lo; r < hi; ++r) s += Rv1[r] * Rd0[r] + Rdv1[r] * Rd1[r];
-    }
+    for (int r = lo; r < hi; ++r) s += Rv1[r] * Rd0[r] + Rdv1[r] * Rd1[r];
     acc[j] += s;
+  }
+}
+
+// 3D: OUT += the records [lo, hi) of the round, all along axis KA (group
+// reduction described above)
+template <int K, int KA, typename T>
+__device__ __forceinline__ void reduce_axis_3d(const T* REC, int lo, int hi, T* OUT) {
+  using LS = LineShape<K, 3>;
+  constexpr int P = BatchShape<K, 3>::RP, KK = K * K, G = kBatchLines / KK;
+  constexpr int O1 = KA == 0 ? 1 : 0;
+  constexpr int O2 = KA == 2 ? 1 : 2;
+  constexpr int SK = ipow(K, KA), S1 = ipow(K, O1), S2 = ipow(K, O2);
+  const int t = threadIdx.x, grp = t / KK, m = t % KK, i1 = m / K, ik = m % K;
+  if (grp >= G || lo >= hi) return;
+  T acc[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) acc[i] = 0;
+  for (int r = lo + grp; r < hi; r += G) {
+    const T* Rc = REC + r;
+    const T v1 = Rc[(LS::V1 + i1) * P];
+    const T pp = v1 * Rc[(LS::D0 + ik) * P] + Rc[(LS::DV1 + i1) * P] * Rc[(LS::D1 + ik) * P];
+    const T qq = v1 * Rc[(LS::D2 + ik) * P];
+#pragma unroll
+    for (int i2 = 0; i2 < K; ++i2) acc[i2] += Rc[(LS::V2 + i2) * P] * pp + Rc[(LS::DV2 + i2) * P] * qq;
+  }
+  // the groups meet in the cell's row through LDS atomic adds
+  T* row = OUT + ik * SK + i1 * S1;
+#pragma unroll
+  for (int i2 = 0; i2 < K; ++i2) {
+    if constexpr (G == 1) row[i2 * S2] += acc[i2];
+    else atomicAdd(row + i2 * S2, acc[i2]);
   }
 }
 
@@ -1328,25 +1356,16 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
     const int* ent = W.rec + 4;
-    int rank[ME], ofs[ME + 1], n0[ME], n1[ME];
-#pragma unroll
-    for (int e = 0; e < ME; ++e) {
-      rank[e] = e < ne ? ent[4 * e] : -1;
-      ofs[e] = e < ne ? (ent[4 * e + 2] & OFS) : total;
-      n0[e] = ent[4 * e + 1] & 0xffff;
-      n1[e] = (ent[4 * e + 1] >> 16) & 0xffff;
-    }
-    ofs[ME] = total;
     // point data of the first round, DoFs and rows of v in one round trip
     int2 hd = cur.hd;
     LinePts<T> L;
     if (t < total) line_load_cell<D>(a, hd.y & 0xffffff, hd.x, 0, L);
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
-      W.U[e][l] = x[(int64_t)ent[4 * e] * ND + l];
+      const int64_t ro = (int64_t)ent[4 * e] * ND + l;
+      W.U[e][l] = x[ro];
+      W.OUT[e][l] = v[ro];
     }
-    T acc[ME][NPL];
-    batch_acc_init<K, D, ME, NPL>(v, rank, ne, acc);
     sync();
     for (int base = 0; base < total; base += NT) {
       const int g = base + t;
@@ -1373,18 +1392,32 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
       }
       sync();
       const int r1 = min(total, base + NT);
+      for (int e = 0; e < ne; ++e) {
+        const int a0 = ent[4 * e + 2] & OFS, a3 = e + 1 < ne ? (ent[4 * (e + 1) + 2] & OFS) : total;
+        if (a0 >= r1 || a3 <= base) continue;
+        const int a1 = a0 + (ent[4 * e + 1] & 0xffff), a2 = a1 + ((ent[4 * e + 1] >> 16) & 0xffff);
+        T* out = &W.OUT[0][0] + e * ND;
+        if constexpr (D == 3) {
+          reduce_axis_3d<K, 0>(W.REC, max(a0, base) - base, min(a1, r1) - base, out);
+          reduce_axis_3d<K, 1>(W.REC, max(a1, base) - base, min(a2, r1) - base, out);
+          reduce_axis_3d<K, 2>(W.REC, max(a2, base) - base, min(a3, r1) - base, out);
+        } else {
+          T acc[NPL];
 #pragma unroll
-      for (int e = 0; e < ME; ++e) {
-        if (e < ne && ofs[e] < r1 && ofs[e + 1] > base) {
-          const int a0 = ofs[e], a1 = a0 + n0[e], a2 = a1 + n1[e], a3 = ofs[e + 1];
-          reduce_axis<K, D, 0, NPL>(W.REC, max(a0, base) - base, min(a1, r1) - base, dof_i, acc[e]);
-          reduce_axis<K, D, 1, NPL>(W.REC, max(a1, base) - base, min(a2, r1) - base, dof_i, acc[e]);
-          if constexpr (D == 3) reduce_axis<K, D, 2, NPL>(W.REC, max(a2, base) - base, min(a3, r1) - base, dof_i, acc[e]);
+          for (int j = 0; j < NPL; ++j) acc[j] = 0;
+          reduce_axis_2d<K, 0, NPL>(W.REC, max(a0, base) - base, min(a1, r1) - base, dof_i, acc);
+          reduce_axis_2d<K, 1, NPL>(W.REC, max(a1, base) - base, min(a3, r1) - base, dof_i, acc);
+#pragma unroll
+          for (int j = 0; j < NPL; ++j)
+            if (t + NT * j < ND) out[t + NT * j] += acc[j];
         }
       }
       sync();
     }
-    batch_acc_store<K, D, ME, NPL>(v, rank, ne, acc);
+    for (int idx = t; idx < ne * ND; idx += NT) {
+      const int e = idx / ND, l = idx % ND;
+      v[(int64_t)ent[4 * e] * ND + l] = W.OUT[e][l];
+    }
   }
 }
 
