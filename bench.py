@@ -49,8 +49,8 @@ STAGES = {1: "inside", 2: "cut_structured", 4: "cut_lines", 8: "cut_face_lines"}
 STAGE_KERNELS = {
     "inside": "inside_kron_kernel (inside cells)",
     "cut_structured": "inside_kron_kernel (cut cells, structured faces and ghost penalty)",
-    "cut_lines": "cut_batch_kernel<FACE=false> (volume and interface lines)",
-    "cut_face_lines": "cut_batch_kernel<FACE=true> (cut-face lines)",
+    "cut_lines": "cut_batch_kernel (volume and interface lines)",
+    "cut_face_lines": "cut_face_kernel (cut-face lines)",
 }
 
 
