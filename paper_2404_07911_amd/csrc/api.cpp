@@ -121,7 +121,7 @@ struct ufem_op {
   int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
   int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
           *line_info = nullptr, *cell_desc = nullptr, *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr,
-          *fdesc = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
+          *fdesc = nullptr, *kinfo_inside = nullptr, *kinfo_cut = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   // per-precision data
   struct Prec {
@@ -210,6 +210,8 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.line_first = line_first;
   a.line_info = line_info;
   a.cell_desc = cell_desc;
+  a.kinfo_inside = kinfo_inside;
+  a.kinfo_cut = kinfo_cut;
   a.vbrec = vbrec;
   a.vdesc = vdesc;
   a.fbrec = fbrec;
@@ -546,6 +548,18 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         sax.push_back(f.axis);
       }
     op->n_sfaces = (int32_t)sbm.size();
+    // per-position cell info of the Kronecker kernel's lists
+    auto make_kinfo = [&](const std::vector<int32_t>& list) {
+      std::vector<int32_t> ki(list.size() * 8, -1);
+      for (size_t i = 0; i < list.size(); ++i) {
+        const int32_t r = list[i];
+        ki[8 * i] = r;
+        ki[8 * i + 1] = flags[r];
+        for (int sl = 0; sl < S; ++sl) ki[8 * i + 2 + sl] = nb[(size_t)r * S + sl];
+      }
+      return ki;
+    };
+    const std::vector<int32_t> kin = make_kinfo(P.inside), kcu = make_kinfo(P.cut);
     std::vector<int32_t> vb, vl, fb, fl;
     make_batches(false, vb, vl, op->n_vbatch);
     make_batches(true, fb, fl, op->n_fbatch);
@@ -562,6 +576,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->cell_line_off, cloff)) || (rc = op->upload((void**)&op->face_lbeg, flb)) ||
         (rc = op->upload((void**)&op->face_lend, fle)) || (rc = op->upload((void**)&op->line_first, P.line_first)) ||
         (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc)) ||
+        (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
         (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
         (rc = op->upload((void**)&op->fbrec, fb)) || (rc = op->upload((void**)&op->fdesc, fl)) ||
         (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||

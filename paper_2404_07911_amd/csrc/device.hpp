@@ -83,6 +83,10 @@ struct DevArgs {
   const int32_t* cell_desc;      // [n_cut * 24] line segments of each cut cell
   // line batches (layout above): volume / interface lines of cut cells and
   // cut-face lines; records and line descriptors
+  // per position of the inside / cut list: (active rank, flags, neighbour
+  // ranks of the 2d slots, -1 padding), 8 ints
+  const int32_t* kinfo_inside;
+  const int32_t* kinfo_cut;
   const int32_t* vbrec;
   const int32_t* vdesc;
   const int32_t* fbrec;

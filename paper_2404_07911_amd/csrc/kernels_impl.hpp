@@ -841,7 +841,7 @@ __device__ __forceinline__ void glb_line_load(const T* __restrict__ src, int bas
 //   v = hs [ M_z (M_y R_x + M_x R_y) + M_y M_x R_z ]
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
-                                                         const int32_t* __restrict__ list, int n_list, int with_volume) {
+                                                         const int32_t* __restrict__ kinfo, int n_list, int with_volume) {
   constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
   __shared__ KronWork<K, D, T> W;
   const T* __restrict__ tab = a.tab;
@@ -854,10 +854,16 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
   for (int c0 = xcd_block() * C; c0 < n_list; c0 += gridDim.x * C) {
     const int ci = c0 + c;
     const bool valid = active && ci < n_list;
-    const int r = valid ? list[ci] : 0;
-    const int fl = valid ? a.flags[r] : 0;
-    // global reads of the cell: own x-line and the neighbours' lines through
+    // the cell's rank, flags and neighbours in one load, then every global
+    // read of the cell at once: own x-line and the neighbours' lines through
     // this lane's face nodes of the x-, y- and z-faces
+    int4 k0 = make_int4(0, 0, 0, 0), k1 = make_int4(0, 0, 0, 0);
+    if (valid) {
+      k0 = reinterpret_cast<const int4*>(kinfo)[2 * ci];
+      k1 = reinterpret_cast<const int4*>(kinfo)[2 * ci + 1];
+    }
+    const int r = k0.x, fl = k0.y;
+    const int nbr[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
     T ux[K], nb[2 * D][K];
     const int bx = line_base<K, D, 0>(l), by = line_base<K, D, 1>(l);
     const int bz = D == 3 ? line_base<K, D, 2>(l) : 0;
@@ -866,7 +872,7 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
 #pragma unroll
       for (int s = 0; s < 2 * D; ++s) {
         if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
-        const T* un = x + (int64_t)a.nb[(int64_t)r * 2 * D + s] * ND;
+        const T* un = x + (int64_t)nbr[s] * ND;
         const int ax = s >> 1;
         if (ax == 0) glb_line_load<K, D, 0>(un, bx, nb[s]);
         else if (ax == 1) glb_line_load<K, D, 1>(un, by, nb[s]);
@@ -2102,7 +2108,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     if (a.kappa == nullptr) {
       constexpr int CW = KronShape<K, D>::C;
       const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
-      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.inside, a.n_inside, 1);
+      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
     } else {
       if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
     }
@@ -2112,7 +2118,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       // lines are added
       constexpr int CW = KronShape<K, D>::C;
       const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
-      if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.cut_rank, a.n_cut, 0);
+      if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
       if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
         static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
         const int g = std::min(a.n_vbatch, nb * a.n_cu);
