@@ -1366,11 +1366,17 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
     int2 hd = cur.hd;
     LinePts<T> L;
     if (t < total) line_load_cell<D>(a, hd.y & 0xffffff, hd.x, 0, L);
-    for (int idx = t; idx < ne * ND; idx += NT) {
+    // (a loop of fixed trip count: every load is issued before the first
+    // LDS store waits for one)
+    // (indices clamped into the batch, so that the loads need no guard)
+#pragma unroll
+    for (int it = 0; it < (ME * ND + NT - 1) / NT; ++it) {
+      const int idx = min(t + NT * it, ne * ND - 1);
       const int e = idx / ND, l = idx % ND;
       const int64_t ro = (int64_t)ent[4 * e] * ND + l;
-      W.U[e][l] = x[ro];
-      W.OUT[e][l] = v[ro];
+      const T xu = x[ro], xv = v[ro];
+      W.U[e][l] = xu;
+      W.OUT[e][l] = xv;
     }
     sync();
     for (int base = 0; base < total; base += NT) {
@@ -1387,9 +1393,9 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
         const T* Uo = &W.U[0][0] + e * ND;
         if (kind == 0 ? do_vol : do_surf) {
           done = true;
-          if (ax == 0) line_work_cell<K, D, 0, RP>(W.tab, a, info, hd.x, L, Uo, W.REC, t);
-          else if (ax == 1 || D == 2) line_work_cell<K, D, 1, RP>(W.tab, a, info, hd.x, L, Uo, W.REC, t);
-          else if constexpr (D == 3) line_work_cell<K, D, 2, RP>(W.tab, a, info, hd.x, L, Uo, W.REC, t);
+          if (ax == 0) line_work_cell<K, D, 0, RP>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
+          else if (ax == 1 || D == 2) line_work_cell<K, D, 1, RP>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
+          else if constexpr (D == 3) line_work_cell<K, D, 2, RP>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
         }
       }
       if (!done) {
@@ -1579,8 +1585,11 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
     int2 hd = cur.hd;
     LinePts<T> L;
     if (t < total) line_load_face<D>(a, hd.y & 0xffffff, hd.x, 0, L);
-    // traces of cell and neighbour on the face node grid (A, B)
-    for (int idx = t; idx < ne * NF; idx += NT) {
+    // traces of cell and neighbour on the face node grid (A, B); a loop of
+    // fixed trip count, so that all loads are issued before the first wait
+#pragma unroll
+    for (int it = 0; it < (ME * NF + NT - 1) / NT; ++it) {
+      const int idx = min(t + NT * it, ne * NF - 1);  // clamped: unguarded loads
       const int e = idx / NF, o = idx % NF;
       const int sl = ent[4 * e + 2] >> kBatchOffsetBits, N = sl >> 1;
       const int ia = o / (D == 3 ? K : 1), ib = D == 3 ? o % K : 0;
@@ -1646,7 +1655,7 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
         }
         const int info = hd.y & 0xffffff, e = hd.y >> 24;
         const int slot = ent[4 * e + 2] >> kBatchOffsetBits;
-        line_work_face<K, D, RP>(W.tab, a, info, hd.x, slot, L, W.TR[e], W.REC, t);
+        line_work_face<K, D, RP>(a.tab, a, info, hd.x, slot, L, W.TR[e], W.REC, t);
       } else {
 #pragma unroll
         for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
