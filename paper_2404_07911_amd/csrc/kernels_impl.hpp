@@ -1009,6 +1009,10 @@ struct LineShape {
   static constexpr int RS = D == 3 ? 7 * K : 4 * K;
   static constexpr int V1 = 0, DV1 = K, V2 = 2 * K, DV2 = 3 * K, D0 = D == 3 ? 4 * K : 2 * K,
                        D1 = D0 + K, D2 = D0 + 2 * K;
+  // records are stored one after the other with this stride (= 2 mod 4
+  // elements: 16-byte aligned records whose pair accesses by consecutive
+  // lanes fall into distinct bank groups)
+  static constexpr int RSP = RS + ((2 - RS % 4) + 4) % 4;
 };
 
 // columns along axis KA of the DoF tensor u contracted with (V1, dV1) over
@@ -1055,21 +1059,22 @@ __device__ __forceinline__ void line_columns(const T* u, const T* V1, const T* d
   }
 }
 
-// store a line record (layout of LineShape) into column r of REC (pitch RP)
-template <int K, int D, int RP, typename T>
+// store a line record (layout of LineShape) as record r of REC
+template <int K, int D, typename T>
 __device__ __forceinline__ void line_record(const T* V1, const T* dV1, const T* V2, const T* dV2, const T* D0,
                                             const T* D1, const T* D2, T* REC, int r) {
   using LS = LineShape<K, D>;
+  T* R = REC + r * LS::RSP;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    REC[(LS::V1 + i) * RP + r] = V1[i];
-    REC[(LS::DV1 + i) * RP + r] = dV1[i];
-    REC[(LS::D0 + i) * RP + r] = D0[i];
-    REC[(LS::D1 + i) * RP + r] = D1[i];
+    R[LS::V1 + i] = V1[i];
+    R[LS::DV1 + i] = dV1[i];
+    R[LS::D0 + i] = D0[i];
+    R[LS::D1 + i] = D1[i];
     if constexpr (D == 3) {
-      REC[(LS::V2 + i) * RP + r] = V2[i];
-      REC[(LS::DV2 + i) * RP + r] = dV2[i];
-      REC[(LS::D2 + i) * RP + r] = D2[i];
+      R[LS::V2 + i] = V2[i];
+      R[LS::DV2 + i] = dV2[i];
+      R[LS::D2 + i] = D2[i];
     }
   }
 }
@@ -1119,9 +1124,9 @@ __device__ __forceinline__ void line_load_cell(const DevArgs<T>& a, int info, in
 
 // one volume or interface line of points along cell axis KA whose first
 // point data are in L: evaluate, apply the point flux, integrate along the
-// line; writes the line record to column r of REC.  info / p0: the line
+// line; writes the line record as record r of REC.  info / p0: the line
 // descriptor (count | axis << 16 | kind << 20, first point)
-template <int K, int D, int KA, int RP, typename T>
+template <int K, int D, int KA, typename T>
 __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a, int info, int p0, LinePts<T>& L,
                                                const T* Uo, T* REC, int r) {
   const T* Xn = tab + TabOff::X(K);
@@ -1179,7 +1184,7 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
       }
     }
   }
-  line_record<K, D, RP>(V1, dV1, V2, dV2, D0, D1, D2, REC, r);
+  line_record<K, D>(V1, dV1, V2, dV2, D0, D1, D2, REC, r);
 }
 
 // Batched line kernels: one wave per batch of cut cells whose lines fit in
@@ -1285,7 +1290,7 @@ struct BatchWork {
   T tab[TabOff::size(K)];
   T U[ME][ND];
   T OUT[ME][ND];
-  T REC[RS * RP];  // component c of the round's record r at REC[c * RP + r]
+  T REC[kBatchLines * LineShape<K, D>::RSP];  // the round's records
   int rec[batch_record_ints(ME)];
 };
 
@@ -1293,18 +1298,15 @@ struct BatchWork {
 template <int K, int KA, int NPL, typename T>
 __device__ __forceinline__ void reduce_axis_2d(const T* REC, int lo, int hi, const int (*dof_i)[3], T* acc) {
   using LS = LineShape<K, 2>;
-  constexpr int P = BatchShape<K, 2>::RP;
   constexpr int O1 = KA == 0 ? 1 : 0;
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
     const int ik = dof_i[j][KA], i1 = dof_i[j][O1];
-    const T* Rv1 = REC + (LS::V1 + i1) * P;
-    const T* Rdv1 = REC + (LS::DV1 + i1) * P;
-    const T* Rd0 = REC + (LS::D0 + ik) * P;
-    const T* Rd1 = REC + (LS::D1 + ik) * P;
     T s = 0;
-#pragma unroll 2
-    for (int r = lo; r < hi; ++r) s += Rv1[r] * Rd0[r] + Rdv1[r] * Rd1[r];
+    for (int r = lo; r < hi; ++r) {
+      const T* R = REC + r * LS::RSP;
+      s += R[LS::V1 + i1] * R[LS::D0 + ik] + R[LS::DV1 + i1] * R[LS::D1 + ik];
+    }
     acc[j] += s;
   }
 }
@@ -1314,7 +1316,7 @@ __device__ __forceinline__ void reduce_axis_2d(const T* REC, int lo, int hi, con
 template <int K, int KA, typename T>
 __device__ __forceinline__ void reduce_axis_3d(const T* REC, int lo, int hi, T* OUT) {
   using LS = LineShape<K, 3>;
-  constexpr int P = BatchShape<K, 3>::RP, KK = K * K, G = kBatchLines / KK;
+  constexpr int KK = K * K, G = kBatchLines / KK;
   constexpr int O1 = KA == 0 ? 1 : 0;
   constexpr int O2 = KA == 2 ? 1 : 2;
   constexpr int SK = ipow(K, KA), S1 = ipow(K, O1), S2 = ipow(K, O2);
@@ -1324,12 +1326,13 @@ __device__ __forceinline__ void reduce_axis_3d(const T* REC, int lo, int hi, T* 
 #pragma unroll
   for (int i = 0; i < K; ++i) acc[i] = 0;
   for (int r = lo + grp; r < hi; r += G) {
-    const T* Rc = REC + r;
-    const T v1 = Rc[(LS::V1 + i1) * P];
-    const T pp = v1 * Rc[(LS::D0 + ik) * P] + Rc[(LS::DV1 + i1) * P] * Rc[(LS::D1 + ik) * P];
-    const T qq = v1 * Rc[(LS::D2 + ik) * P];
+    const T* R = REC + r * LS::RSP;
+    const T v1 = R[LS::V1 + i1];
+    const T pp = v1 * R[LS::D0 + ik] + R[LS::DV1 + i1] * R[LS::D1 + ik];
+    const T qq = v1 * R[LS::D2 + ik];
+    // V2, dV2: the same for the whole group, consecutive in the record
 #pragma unroll
-    for (int i2 = 0; i2 < K; ++i2) acc[i2] += Rc[(LS::V2 + i2) * P] * pp + Rc[(LS::DV2 + i2) * P] * qq;
+    for (int i2 = 0; i2 < K; ++i2) acc[i2] += R[LS::V2 + i2] * pp + R[LS::DV2 + i2] * qq;
   }
   // the groups meet in the cell's row through LDS atomic adds
   T* row = OUT + ik * SK + i1 * S1;
@@ -1393,14 +1396,14 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
         const T* Uo = &W.U[0][0] + e * ND;
         if (kind == 0 ? do_vol : do_surf) {
           done = true;
-          if (ax == 0) line_work_cell<K, D, 0, RP>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
-          else if (ax == 1 || D == 2) line_work_cell<K, D, 1, RP>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
-          else if constexpr (D == 3) line_work_cell<K, D, 2, RP>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
+          if (ax == 0) line_work_cell<K, D, 0>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
+          else if (ax == 1 || D == 2) line_work_cell<K, D, 1>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
+          else if constexpr (D == 3) line_work_cell<K, D, 2>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
         }
       }
       if (!done) {
 #pragma unroll
-        for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
+        for (int c = 0; c < RS; ++c) W.REC[t * LineShape<K, D>::RSP + c] = 0;
       }
       sync();
       const int r1 = min(total, base + NT);
