@@ -45,10 +45,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-STAGES = {1: "inside", 2: "cut_structured", 4: "cut_lines", 8: "cut_face_lines"}
+# kernel stages of one apply (ufem_apply_part masks): the Kronecker kernel over
+# inside cells and the structured faces of cut cells (one launch), the
+# volume / interface lines, the cut-face lines
+STAGES = {3: "structured", 4: "cut_lines", 8: "cut_face_lines"}
 STAGE_KERNELS = {
-    "inside": "inside_kron_kernel (inside cells)",
-    "cut_structured": "inside_kron_kernel (cut cells, structured faces and ghost penalty)",
+    "structured": "inside_kron_kernel (inside cells; structured faces and ghost penalty of cut cells)",
     "cut_lines": "cut_batch_kernel (volume and interface lines)",
     "cut_face_lines": "cut_face_kernel (cut-face lines)",
 }
@@ -58,9 +60,9 @@ def model(info, dim, p, s):
     """Algorithmic bytes per kernel stage and model FLOPs of one apply.
 
     Bytes (s = bytes per value) count what a stage must move at the least:
-    the rows of u it reads and of v it writes for its own cells (inside: read
-    u, write v; cut structured: read u, write v; the two line stages add to
-    v, so read u, read and write v), and the quadrature data of the cut cells
+    the rows of u it reads and of v it writes for its own cells (structured:
+    read u, write v of inside and cut cells; the two line stages add to v, so
+    read u, read and write v of cut cells), and the quadrature data of the cut cells
     (volume point: dim coordinates and a weight; interface point: dim
     coordinates, a weight and dim normal components; cut-face point: dim - 1
     in-face coordinates and a weight).  Index tables are not counted.
@@ -77,8 +79,7 @@ def model(info, dim, p, s):
     n_fcut = seg[4] - seg[3]
     n_surf = seg[5] - seg[4]
     b = {
-        "inside": info["n_inside"] * nd * 2 * s,
-        "cut_structured": info["n_cut"] * nd * 2 * s,
+        "structured": (info["n_inside"] + info["n_cut"]) * nd * 2 * s,
         "cut_lines": info["n_cut"] * nd * 3 * s + n_vol * (dim + 1) * s + n_surf * (2 * dim + 1) * s,
         "cut_face_lines": info["n_cut"] * nd * 3 * s + n_fcut * dim * s,
     }
@@ -282,7 +283,8 @@ def main(argv=None):
     # one step: the FP64 apply and the FP32 apply stage by stage (each stage
     # one kernel, bracketed by events on the library's stream), then the FP64
     # adjoint pass
-    NEV = 10
+    NS = len(STAGES)
+    NEV = 2 * NS + 2
 
     def step(i, ev=None):
         j = i % npairs
@@ -294,10 +296,10 @@ def main(argv=None):
                 k += 1
                 op.apply_part(part, U, V)
         if ev is not None:
-            ev[8].record(stream)
+            ev[2 * NS].record(stream)
         op.apply_adjoint(W64, U64[j], ATW, DK)
         if ev is not None:
-            ev[9].record(stream)
+            ev[2 * NS + 1].record(stream)
 
     for i in range(args.warmup):
         step(i)
@@ -315,11 +317,11 @@ def main(argv=None):
 
     names = list(STAGES.values())
     ms64 = {nm: mean_ms(q, q + 1) for q, nm in enumerate(names)}
-    ms32 = {nm: mean_ms(4 + q, 4 + q + 1) for q, nm in enumerate(names)}
-    adj = mean_ms(8, 9)
-    step_ms = mean_ms(0, 9)
-    t64 = mean_ms(0, 4) * 1e-3
-    t32 = mean_ms(4, 8) * 1e-3
+    ms32 = {nm: mean_ms(NS + q, NS + q + 1) for q, nm in enumerate(names)}
+    adj = mean_ms(2 * NS, 2 * NS + 1)
+    step_ms = mean_ms(0, 2 * NS + 1)
+    t64 = mean_ms(0, NS) * 1e-3
+    t32 = mean_ms(NS, 2 * NS) * 1e-3
     tadj = adj * 1e-3
 
     # correctness spot check of the timed FP64 result against a fresh apply

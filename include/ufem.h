@@ -166,9 +166,10 @@ int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* str
 
 /* The kernel stages of ufem_apply (UFEM_PART_* bits, any non-empty mask),
  * for per-kernel timing; UFEM_PART_ALL is ufem_apply.  Stages run in the
- * order 1, 2, 4, 8 on `stream`; rows of the cells a mask does not cover are
- * left untouched, and stages 4 and 8 add to v, so the rows of cut cells are
- * A u only when stages 2, 4 and 8 run after one another (in one call or in
+ * order 1, 2, 4, 8 on `stream` (with kappa = 1, stages 1 and 2 requested
+ * together are one kernel); rows of the cells a mask does not cover are left
+ * untouched, and stages 4 and 8 add to v, so the rows of cut cells are A u
+ * only when stages 2, 4 and 8 run after one another (in one call or in
  * consecutive calls with the same u and v).  EINVAL for an empty or unknown
  * mask. */
 int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u, void* v, void* stream);

@@ -121,7 +121,7 @@ struct ufem_op {
   int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
   int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
           *line_info = nullptr, *cell_desc = nullptr, *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr,
-          *fdesc = nullptr, *kinfo_inside = nullptr, *kinfo_cut = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
+          *fdesc = nullptr, *kinfo_inside = nullptr, *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   // per-precision data
   struct Prec {
@@ -212,6 +212,7 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.cell_desc = cell_desc;
   a.kinfo_inside = kinfo_inside;
   a.kinfo_cut = kinfo_cut;
+  a.kinfo_all = kinfo_all;
   a.vbrec = vbrec;
   a.vdesc = vdesc;
   a.fbrec = fbrec;
@@ -560,6 +561,22 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       return ki;
     };
     const std::vector<int32_t> kin = make_kinfo(P.inside), kcu = make_kinfo(P.cut);
+    // both lists merged in rank (background) order, so that every XCD's
+    // contiguous range gets its share of the cheaper cut cells and neighbours
+    // stay close
+    std::vector<int32_t> kall;
+    kall.reserve(kin.size() + kcu.size());
+    for (size_t i = 0, j = 0; i < P.inside.size() || j < P.cut.size();) {
+      const bool take_cut = i == P.inside.size() || (j < P.cut.size() && P.cut[j] < P.inside[i]);
+      if (take_cut) {
+        kall.insert(kall.end(), kcu.begin() + 8 * j, kcu.begin() + 8 * (j + 1));
+        kall[kall.size() - 7] |= 1 << ufem::kFlagNoVolume;
+        ++j;
+      } else {
+        kall.insert(kall.end(), kin.begin() + 8 * i, kin.begin() + 8 * (i + 1));
+        ++i;
+      }
+    }
     std::vector<int32_t> vb, vl, fb, fl;
     make_batches(false, vb, vl, op->n_vbatch);
     make_batches(true, fb, fl, op->n_fbatch);
@@ -577,6 +594,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->face_lend, fle)) || (rc = op->upload((void**)&op->line_first, P.line_first)) ||
         (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc)) ||
         (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
+        (rc = op->upload((void**)&op->kinfo_all, kall)) ||
         (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
         (rc = op->upload((void**)&op->fbrec, fb)) || (rc = op->upload((void**)&op->fdesc, fl)) ||
         (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||

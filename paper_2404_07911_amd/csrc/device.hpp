@@ -12,6 +12,8 @@ namespace ufem {
 // flags word of an active cell: bit s -> ghost penalty on slot s,
 // bit 8 + s -> structured SIPG, bit 16 + s -> cut SIPG.
 constexpr int kFlagGP = 0, kFlagStr = 8, kFlagCut = 16;
+// in the combined list of the Kronecker kernel: a cut cell (faces only)
+constexpr int kFlagNoVolume = 24;
 
 // Table layout (per precision), K = p + 1:
 //   S [K*K]   S[q*K+i]  = L_i(g_q), GLL Lagrange basis at the Gauss points
@@ -87,6 +89,7 @@ struct DevArgs {
   // ranks of the 2d slots, -1 padding), 8 ints
   const int32_t* kinfo_inside;
   const int32_t* kinfo_cut;
+  const int32_t* kinfo_all;  // both, in rank order, cut cells flagged kFlagNoVolume
   const int32_t* vbrec;
   const int32_t* vdesc;
   const int32_t* fbrec;

@@ -850,7 +850,9 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
   const int lane = threadIdx.x;
   const int c = lane / NL, l = lane % NL;
   const bool active = c < C;
-  const bool vol = with_volume && (a.terms & 1) != 0;
+  // cells flagged kFlagNoVolume (cut cells in the combined list) take the
+  // faces only
+  const bool vol_all = with_volume && (a.terms & 1) != 0;
   for (int c0 = xcd_block() * C; c0 < n_list; c0 += gridDim.x * C) {
     const int ci = c0 + c;
     const bool valid = active && ci < n_list;
@@ -863,6 +865,7 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
       k1 = reinterpret_cast<const int4*>(kinfo)[2 * ci + 1];
     }
     const int r = k0.x, fl = k0.y;
+    const bool vol = vol_all && !((fl >> kFlagNoVolume) & 1);
     const int nbr[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
     T ux[K], nb[2 * D][K];
     const int bx = line_base<K, D, 0>(l), by = line_base<K, D, 1>(l);
@@ -2117,7 +2120,14 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
   }
   if (!adj) {
     const bool fast_cut = a.kappa == nullptr;
-    if (a.kappa == nullptr) {
+    const bool both = a.kappa == nullptr && (a.parts & 3) == 3;
+    if (both) {
+      // inside cells and the structured faces of the cut cells in one launch
+      constexpr int CW = KronShape<K, D>::C;
+      const int64_t n_all = a.n_inside + a.n_cut;
+      const int gk = (int)std::min<int64_t>((n_all + CW - 1) / CW, 1 << 20);
+      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_all, (int)n_all, 1);
+    } else if (a.kappa == nullptr) {
       constexpr int CW = KronShape<K, D>::C;
       const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
       if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
@@ -2129,7 +2139,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       // their rows), then the volume / interface lines and the cut-face
       // lines are added
       constexpr int CW = KronShape<K, D>::C;
-      const int gs = (a.parts & 2) ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
+      const int gs = (a.parts & 2) && !both ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
       if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
       if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
         static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);

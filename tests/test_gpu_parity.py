@@ -128,10 +128,11 @@ def test_apply_stages_compose(torch, name):
             _say(f"[{name}] stages, kappa {'field' if k is not None else '1'}")
             op.set_kappa(k)
             full = op.apply(ud)
-            v = torch.full_like(ud, float("nan"))
-            for part in (1, 2, 4, 8):
-                op.apply_part(part, ud, v)
-            assert torch.equal(v, full)
+            for parts in ((1, 2, 4, 8), (3, 4, 8), (1, 2, 12)):
+                v = torch.full_like(ud, float("nan"))
+                for part in parts:
+                    op.apply_part(part, ud, v)
+                assert torch.equal(v, full), parts
             v = torch.full_like(ud, float("nan"))
             op.apply_part(PART_INSIDE, ud, v)
             op.apply_part(PART_CUT, ud, v)
