@@ -56,7 +56,7 @@ STAGE_KERNELS = {
 }
 
 
-def model(info, dim, p, s):
+def model(info, dim, p, s, kappa=False):
     """Algorithmic bytes per kernel stage and model FLOPs of one apply.
 
     Bytes (s = bytes per value) count what a stage must move at the least:
@@ -65,7 +65,8 @@ def model(info, dim, p, s):
     read u, read and write v of cut cells), and the quadrature data of the cut cells
     (volume point: dim coordinates and a weight; interface point: dim
     coordinates, a weight and dim normal components; cut-face point: dim - 1
-    in-face coordinates and a weight).  Index tables are not counted.
+    in-face coordinates and a weight), plus one kappa value per quadrature
+    point when a coefficient field is set.  Index tables are not counted.
     FLOPs: the paper's operation counts (Section 5.1) for 3D: 24 k^4 per
     structured cell, 56 k^3 per structured face (both sides, evaluation and
     integration), 4 (2k^3 + 3k^2 + 4k) per unstructured cell or interface
@@ -85,6 +86,12 @@ def model(info, dim, p, s):
     }
     # the whole apply: u read and v written once per DoF, plus the point data
     b["total"] = info["n_dofs"] * 2 * s + n_vol * (dim + 1) * s + n_surf * (2 * dim + 1) * s + n_fcut * dim * s
+    if kappa:
+        k_str = (seg[1] - seg[0]) + (seg[3] - seg[2])
+        b["structured"] += k_str * s
+        b["cut_lines"] += (n_vol + n_surf) * s
+        b["cut_face_lines"] += n_fcut * s
+        b["total"] += info["n_qp"] * s
     flops = None
     if dim == 3:
         flops = (
@@ -263,6 +270,10 @@ def main(argv=None):
     t_setup = time.perf_counter() - t0
     info = plan.info
     n = info["n_dofs"]
+    with_kappa = wl.name == "kappa3d"
+    if with_kappa:
+        # variable coefficient at every quadrature point (the kappa workload)
+        op.set_kappa(torch.from_numpy(ui.kappa_field(plan.qp()[0])).to(dev))
     if args.mode == "solve":
         return solve_mode(args, wl, rng, plan, op, t_setup)
     u_host = ui.uniform_vector(rng, n)
@@ -329,8 +340,8 @@ def main(argv=None):
     torch.cuda.synchronize()
     assert torch.isfinite(vchk).all()
 
-    bytes64, flops = model(info, wl.dim, wl.degree, 8)
-    bytes32, _ = model(info, wl.dim, wl.degree, 4)
+    bytes64, flops = model(info, wl.dim, wl.degree, 8, with_kappa)
+    bytes32, _ = model(info, wl.dim, wl.degree, 4, with_kappa)
     dom = max(ms64, key=ms64.get)
     dom_ms = ms64[dom]
     achieved = bytes64[dom] / (dom_ms * 1e-3) / 1e9
@@ -368,6 +379,7 @@ def main(argv=None):
             "background_cells": wl.n,
             "active_dofs": n,
             "background_dofs": info["n_background"] * (wl.degree + 1) ** wl.dim,
+            "kappa": "1 + 0.5 sin(pi x) sin(pi y) sin(pi z) per quadrature point" if with_kappa else "1",
             "inside_cells": info["n_inside"],
             "cut_cells": info["n_cut"],
             "quadrature_points": info["n_qp"],

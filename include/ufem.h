@@ -60,12 +60,11 @@ enum {
 enum { UFEM_F64 = 0, UFEM_F32 = 1 };
 
 /* Kernel stages of one apply (ufem_apply_part).  Stage 1 writes the rows of
- * inside cells.  Stage 2 writes the rows of cut cells: with kappa = 1 only
- * their structured-face and ghost-penalty terms (sum factorisation), with a
- * kappa field the whole cut cell.
- * Stages 4 and 8 add the dimension-reduction volume and interface lines and
- * the cut-face lines to the rows stage 2 wrote (no work where stage 2 already
- * did the whole cell). */
+ * inside cells.  Stage 2 writes the rows of cut cells with their
+ * structured-face and ghost-penalty terms (sum factorisation with kappa = 1,
+ * per-point face quadrature with a kappa field).  Stages 4 and 8 add the
+ * dimension-reduction volume and interface lines and the cut-face lines to
+ * the rows stage 2 wrote. */
 enum {
   UFEM_PART_INSIDE = 1,
   UFEM_PART_CUT_STRUCTURED = 2,

@@ -151,8 +151,25 @@ struct Work {
   T acc[ND];
   T t[5][ND];
   T f[6][NF];
-  T pts[Shape<K, D>::PC * Shape<K, D>::PT];
+  T pts[ADJ ? Shape<K, D>::PC * Shape<K, D>::PT : 1];  // point records (adjoint pass)
+  T nbuf[ADJ ? 1 : 2 * D][ADJ ? 1 : ND];              // all neighbours (apply)
 };
+
+// the apply's neighbours of a cell, all loaded at once (slots with a
+// structured SIPG or ghost-penalty term)
+template <int K, int D, typename T, bool ADJ>
+__device__ __forceinline__ void load_neighbours(Work<K, D, T, ADJ>& W, const T* __restrict__ x, const int* nbr,
+                                                int fl, int terms) {
+  constexpr int ND = Shape<K, D>::ND;
+  if constexpr (!ADJ) {
+#pragma unroll
+    for (int s = 0; s < 2 * D; ++s) {
+      const bool on = ((terms & 2) && ((fl >> (kFlagStr + s)) & 1)) || ((terms & 8) && ((fl >> (kFlagGP + s)) & 1));
+      if (!on) continue;
+      for (int l = threadIdx.x; l < ND; l += blockDim.x) W.nbuf[s][l] = x[(int64_t)nbr[s] * ND + l];
+    }
+  }
+}
 
 // cell index of in-face node f at layer l along `axis`
 template <int K, int D>
@@ -604,20 +621,28 @@ __global__ void __launch_bounds__((Shape<K, D>::NT)) inside_kernel(DevArgs<T> a,
   __shared__ Work<K, D, T, ADJ> W;
   load_tab<K, D>(W, a.tab);
   for (int ci = blockIdx.x; ci < a.n_inside; ci += gridDim.x) {
-    const int r = a.inside[ci];
+    // rank, flags and neighbours in one load (uniform across the block)
+    const int4 k0 = reinterpret_cast<const int4*>(a.kinfo_inside)[2 * ci];
+    const int4 k1 = reinterpret_cast<const int4*>(a.kinfo_inside)[2 * ci + 1];
+    const int r = k0.x, fl = k0.y;
+    const int nbrs[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
     load_cell<K, D, T, ADJ>(W.xo, x, r);
     if constexpr (ADJ) load_cell<K, D, T, ADJ>(W.yo, y, r);
+    load_neighbours<K, D>(W, x, nbrs, fl, a.terms);
     for (int l = threadIdx.x; l < ND; l += blockDim.x) W.acc[l] = 0;
     sync();
     if (a.terms & 1) volume_structured<K, D>(W, a, a.seg[0] + (int64_t)ci * ND, dkappa);
-    const int fl = a.flags[r];
     for (int s = 0; s < 2 * D; ++s) {
       const bool sipg = (a.terms & 2) && ((fl >> (kFlagStr + s)) & 1);
       const bool gp = (a.terms & 8) && ((fl >> (kFlagGP + s)) & 1);
       if (!sipg && !gp) continue;
-      const int nbr = a.nb[(int64_t)r * 2 * D + s];
-      load_cell<K, D, T, ADJ>(W.xn, x, nbr);
-      if constexpr (ADJ) load_cell<K, D, T, ADJ>(W.yn, y, nbr);
+      const int nbr = nbrs[s];
+      if constexpr (ADJ) {
+        load_cell<K, D, T, ADJ>(W.xn, x, nbr);
+        load_cell<K, D, T, ADJ>(W.yn, y, nbr);
+      } else {
+        for (int l = threadIdx.x; l < ND; l += blockDim.x) W.xn[l] = W.nbuf[s][l];
+      }
       sync();
       if (sipg) {
         const int fid = a.slot_face[(int64_t)r * 2 * D + s];
@@ -640,32 +665,46 @@ __global__ void __launch_bounds__((Shape<K, D>::NT)) cut_kernel(DevArgs<T> a, co
   load_tab<K, D>(W, a.tab);
   for (int slot = blockIdx.x; slot < a.n_cut; slot += gridDim.x) {
     const int ci = a.cut_order[slot];
-    const int r = a.cut_rank[ci];
+    const int4 k0 = reinterpret_cast<const int4*>(a.kinfo_cut)[2 * ci];
+    const int4 k1 = reinterpret_cast<const int4*>(a.kinfo_cut)[2 * ci + 1];
+    const int r = k0.x, fl = k0.y;
+    const int nbrs[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
     load_cell<K, D, T, ADJ>(W.xo, x, r);
     if constexpr (ADJ) load_cell<K, D, T, ADJ>(W.yo, y, r);
+    load_neighbours<K, D>(W, x, nbrs, fl, a.terms);
     for (int l = threadIdx.x; l < ND; l += blockDim.x) W.acc[l] = 0;
     sync();
-    if (a.terms & 1) {
-      const int64_t q0 = a.vol_off[ci];
-      cut_points<K, D, false>(W, a, q0, (int)(a.vol_off[ci + 1] - q0), a.seg[1] + q0, dkappa);
+    // the apply leaves the volume, interface and cut-face points to the line
+    // kernels (structured faces and ghost penalty only); the adjoint pass
+    // evaluates every term here
+    if constexpr (ADJ) {
+      if (a.terms & 1) {
+        const int64_t q0 = a.vol_off[ci];
+        cut_points<K, D, false>(W, a, q0, (int)(a.vol_off[ci + 1] - q0), a.seg[1] + q0, dkappa);
+      }
+      if (a.terms & 4) {
+        const int64_t q0 = a.surf_off[ci];
+        cut_points<K, D, true>(W, a, q0, (int)(a.surf_off[ci + 1] - q0), a.seg[4] + q0, dkappa);
+      }
     }
-    if (a.terms & 4) {
-      const int64_t q0 = a.surf_off[ci];
-      cut_points<K, D, true>(W, a, q0, (int)(a.surf_off[ci + 1] - q0), a.seg[4] + q0, dkappa);
-    }
-    const int fl = a.flags[r];
     for (int s = 0; s < 2 * D; ++s) {
       const bool str = (a.terms & 2) && ((fl >> (kFlagStr + s)) & 1);
-      const bool cutf = (a.terms & 2) && ((fl >> (kFlagCut + s)) & 1);
+      const bool cutf = ADJ && (a.terms & 2) && ((fl >> (kFlagCut + s)) & 1);
       const bool gp = (a.terms & 8) && ((fl >> (kFlagGP + s)) & 1);
       if (!str && !cutf && !gp) continue;
-      const int nbr = a.nb[(int64_t)r * 2 * D + s];
-      load_cell<K, D, T, ADJ>(W.xn, x, nbr);
-      if constexpr (ADJ) load_cell<K, D, T, ADJ>(W.yn, y, nbr);
+      const int nbr = nbrs[s];
+      if constexpr (ADJ) {
+        load_cell<K, D, T, ADJ>(W.xn, x, nbr);
+        load_cell<K, D, T, ADJ>(W.yn, y, nbr);
+      } else {
+        for (int l = threadIdx.x; l < ND; l += blockDim.x) W.xn[l] = W.nbuf[s][l];
+      }
       sync();
       const int fid = a.slot_face[(int64_t)r * 2 * D + s];
       if (str) face_sipg_structured<K, D>(W, a, s >> 1, s & 1, a.face_qoff[fid], dkappa);
-      if (cutf) face_sipg_cut<K, D>(W, a, s >> 1, s & 1, a.face_qoff[fid], a.face_qn[fid], dkappa);
+      if constexpr (ADJ) {
+        if (cutf) face_sipg_cut<K, D>(W, a, s >> 1, s & 1, a.face_qoff[fid], a.face_qn[fid], dkappa);
+      }
       if (gp) face_ghost<K, D>(W, a, s >> 1, s & 1);
     }
     T* out = v + (int64_t)r * ND;
@@ -2096,7 +2135,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
   constexpr int NT = Shape<K, D>::NT;
   const int gi = (a.parts & 1) ? (int)std::min<int64_t>(a.n_inside, 1 << 20) : 0;
   const int gc = (a.parts & 2) ? (int)std::min<int64_t>(a.n_cut, 1 << 20) : 0;
-  if (adj && a.kappa == nullptr && ipow(K, D) <= 125) {
+  if (adj && ipow(K, D) <= 125) {
     // A is symmetric: A^T w is the fast apply of w; dkappa from the
     // evaluation kernels
     DevArgs<T> b = a;
@@ -2119,7 +2158,6 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     return hipGetLastError();
   }
   if (!adj) {
-    const bool fast_cut = a.kappa == nullptr;
     const bool both = a.kappa == nullptr && (a.parts & 3) == 3;
     if (both) {
       // inside cells and the structured faces of the cut cells in one launch
@@ -2134,13 +2172,19 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     } else {
       if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
     }
-    if (fast_cut) {
+    {
       // structured faces and ghost penalty of the cut cells (overwrites
-      // their rows), then the volume / interface lines and the cut-face
-      // lines are added
+      // their rows: Kronecker kernel with kappa = 1, per-point face
+      // quadrature with kappa), then the volume / interface lines and the
+      // cut-face lines are added
       constexpr int CW = KronShape<K, D>::C;
       const int gs = (a.parts & 2) && !both ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
-      if (gs > 0) inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
+      if (gs > 0) {
+        if (a.kappa == nullptr)
+          inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
+        else if (gc > 0)
+          cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
+      }
       if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
         static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
         const int g = std::min(a.n_vbatch, nb * a.n_cu);
@@ -2151,18 +2195,13 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
         const int g = std::min(a.n_fbatch, nb * a.n_cu);
         cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
       }
-    } else {
-      if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
     }
     return hipGetLastError();
   }
-  if (adj) {
-    if (gi > 0) inside_kernel<K, D, T, true><<<gi, NT, 0, s>>>(a, x, y, v, dk);
-    if (gc > 0) cut_kernel<K, D, T, true><<<gc, NT, 0, s>>>(a, x, y, v, dk);
-  } else {
-    if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
-    if (gc > 0) cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
-  }
+  // adjoint pass with K^d > 125: A^T w and dkappa by the quadrature-path
+  // kernels
+  if (gi > 0) inside_kernel<K, D, T, true><<<gi, NT, 0, s>>>(a, x, y, v, dk);
+  if (gc > 0) cut_kernel<K, D, T, true><<<gc, NT, 0, s>>>(a, x, y, v, dk);
   return hipGetLastError();
 }
 
