@@ -118,7 +118,8 @@ struct ufem_op {
   // integer data
   int32_t *inside = nullptr, *cut_order = nullptr, *cut_rank = nullptr, *nb = nullptr, *flags = nullptr,
           *slot_face = nullptr, *face_qn = nullptr;
-  int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr;
+  int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr, *kface_inside = nullptr,
+          *kface_cut = nullptr;
   int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
           *line_info = nullptr, *cell_desc = nullptr, *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr,
           *fdesc = nullptr, *kinfo_inside = nullptr, *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
@@ -213,6 +214,8 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.kinfo_inside = kinfo_inside;
   a.kinfo_cut = kinfo_cut;
   a.kinfo_all = kinfo_all;
+  a.kface_inside = kface_inside;
+  a.kface_cut = kface_cut;
   a.vbrec = vbrec;
   a.vdesc = vdesc;
   a.fbrec = fbrec;
@@ -561,6 +564,16 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       return ki;
     };
     const std::vector<int32_t> kin = make_kinfo(P.inside), kcu = make_kinfo(P.cut);
+    auto make_kface = [&](const std::vector<int32_t>& list) {
+      std::vector<int64_t> kf(list.size() * S, 0);
+      for (size_t i = 0; i < list.size(); ++i)
+        for (int sl = 0; sl < S; ++sl) {
+          const int32_t fi = P.slot_face[(size_t)list[i] * S + sl];
+          if (fi >= 0) kf[i * S + sl] = P.faces[fi].qp_off;
+        }
+      return kf;
+    };
+    const std::vector<int64_t> kfin = make_kface(P.inside), kfcu = make_kface(P.cut);
     // both lists merged in rank (background) order, so that every XCD's
     // contiguous range gets its share of the cheaper cut cells and neighbours
     // stay close
@@ -594,7 +607,8 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->face_lend, fle)) || (rc = op->upload((void**)&op->line_first, P.line_first)) ||
         (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc)) ||
         (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
-        (rc = op->upload((void**)&op->kinfo_all, kall)) ||
+        (rc = op->upload((void**)&op->kinfo_all, kall)) || (rc = op->upload((void**)&op->kface_inside, kfin)) ||
+        (rc = op->upload((void**)&op->kface_cut, kfcu)) ||
         (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
         (rc = op->upload((void**)&op->fbrec, fb)) || (rc = op->upload((void**)&op->fdesc, fl)) ||
         (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||

@@ -90,6 +90,9 @@ struct DevArgs {
   const int32_t* kinfo_inside;
   const int32_t* kinfo_cut;
   const int32_t* kinfo_all;  // both, in rank order, cut cells flagged kFlagNoVolume
+  // per position and slot: kappa offset of the structured face's points
+  const int64_t* kface_inside;
+  const int64_t* kface_cut;
   const int32_t* vbrec;
   const int32_t* vdesc;
   const int32_t* fbrec;

@@ -1029,6 +1029,340 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
   }
 }
 
+// ------------------------------------------------ structured terms with kappa
+// One wave handles C cells (inside cells with their volume term, or cut
+// cells for their structured faces and ghost penalty), one lane per 1D line
+// as in the Kronecker kernel.  Volume: the reference gradient at the k^d
+// Gauss points by three line passes (S: GLL basis at the Gauss points, DS:
+// its derivative), times w_q kappa_q h^(d-2), and the transposed passes back
+// to the nodes (the paper's structured evaluation, Section 3.2).  Faces
+// (Gauss-Lobatto node grid of the face = the lines along the normal axis):
+// SIPG from the value and normal-derivative traces of both sides,
+// interpolated to the face Gauss points, weighted by w_q kappa_q h^(d-2) and
+// integrated back; ghost penalty from the derivative jumps of every order
+// times the exact in-face mass matrices (no kappa).  Rows are overwritten.
+template <int K, int D, typename T>
+struct KappaWork {
+  static constexpr int NDP = KronLayout<K, D>::NDP, C = KronShape<K, D>::C, NF = ipow(K, D - 1);
+  T A[C][NDP];
+  T B[C][NDP];
+  T Cc[C][NDP];
+  T U[C][NDP];
+  T OUT[C][NDP];
+  T F0[C][NF];
+  T F1[C][NF];
+  T FJ[C][K][NF];  // derivative jumps of every order (ghost penalty)
+};
+
+// y = M^T x along a line (M row-major K x K, uniform across the wave)
+template <int K, typename T>
+__device__ __forceinline__ void line_matT(const T* __restrict__ M, const T* x, T* y) {
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) s += M[q * K + r] * x[q];
+    y[r] = s;
+  }
+}
+
+// in-face transform of a node field F (K^(D-1) values, lower in-face axis
+// fastest) by M1 x M1 (M1 row-major K x K; TR: transposed), value at this
+// lane's node f
+template <int K, int D, bool TR, typename T>
+__device__ __forceinline__ T face_transform(const T* __restrict__ M1, const T* F, int f) {
+  if constexpr (D == 2) {
+    T s = 0;
+#pragma unroll
+    for (int g = 0; g < K; ++g) s += (TR ? M1[g * K + f] : M1[f * K + g]) * F[g];
+    return s;
+  } else {
+    const int f0 = f % K, f1 = f / K;
+    T s = 0;
+#pragma unroll
+    for (int g1 = 0; g1 < K; ++g1) {
+      T t = 0;
+#pragma unroll
+      for (int g0 = 0; g0 < K; ++g0) t += (TR ? M1[g0 * K + f0] : M1[f0 * K + g0]) * F[g0 + K * g1];
+      s += (TR ? M1[g1 * K + f1] : M1[f1 * K + g1]) * t;
+    }
+    return s;
+  }
+}
+
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(64) kappa_struct_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+                                                          const int32_t* __restrict__ kinfo,
+                                                          const int64_t* __restrict__ kface, int n_list,
+                                                          int with_volume) {
+  constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
+  __shared__ KappaWork<K, D, T> W;
+  const T* __restrict__ tab = a.tab;
+  const T* S = tab + TabOff::S(K);
+  const T* DS = tab + TabOff::DS(K);
+  const T* M = tab + TabOff::M(K);
+  const T* Wg = tab + TabOff::W(K);
+  const T* GW = tab + TabOff::GW(K);
+  const int lane = threadIdx.x;
+  const int c = lane / NL, l = lane % NL;
+  const bool active = c < C;
+  const int cc = active ? c : 0;
+  const bool vol_on = with_volume && (a.terms & 1) != 0;
+  const bool sipg_on = (a.terms & 2) != 0, gp_on = (a.terms & 8) != 0;
+  int pos[D][K];
+  KronLayout<K, D>::template line<0>(l, pos[0]);
+  KronLayout<K, D>::template line<1>(l, pos[1]);
+  if constexpr (D == 3) KronLayout<K, D>::template line<2>(l, pos[2]);
+  for (int c0 = xcd_block() * C; c0 < n_list; c0 += gridDim.x * C) {
+    const int ci = c0 + c;
+    const bool valid = active && ci < n_list;
+    int4 k0 = make_int4(0, 0, 0, 0), k1 = make_int4(0, 0, 0, 0);
+    if (valid) {
+      k0 = reinterpret_cast<const int4*>(kinfo)[2 * ci];
+      k1 = reinterpret_cast<const int4*>(kinfo)[2 * ci + 1];
+    }
+    const int r = k0.x, fl = k0.y;
+    const int nbr[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+    const int bx = line_base<K, D, 0>(l), by = line_base<K, D, 1>(l);
+    const int bz = D == 3 ? line_base<K, D, 2>(l) : 0;
+    T ux[K], nb[2 * D][K];
+    int64_t fko[2 * D];
+    if (valid) {
+      glb_line_load<K, D, 0>(x + (int64_t)r * ND, bx, ux);
+#pragma unroll
+      for (int s = 0; s < 2 * D; ++s) {
+        fko[s] = kface[(int64_t)ci * 2 * D + s];
+        if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+        const T* un = x + (int64_t)nbr[s] * ND;
+        const int ax = s >> 1;
+        if (ax == 0) glb_line_load<K, D, 0>(un, bx, nb[s]);
+        else if (ax == 1) glb_line_load<K, D, 1>(un, by, nb[s]);
+        else if constexpr (D == 3) glb_line_load<K, D, 2>(un, bz, nb[s]);
+      }
+    }
+    T* U = W.U[cc];
+    T* A = W.A[cc];
+    T* B = W.B[cc];
+    T* Cc = W.Cc[cc];
+    T* OUT = W.OUT[cc];
+    T t0[K], t1[K], t2[K], t3[K];
+    if (valid) {
+      kl_store<K>(U, pos[0], ux);
+#pragma unroll
+      for (int q = 0; q < K; ++q) t0[q] = 0;
+      kl_store<K>(OUT, pos[0], t0);
+    }
+    sync();
+    // ---- volume
+    const bool vol = vol_on && valid;
+    if constexpr (D == 3) {
+      if (vol) {
+        line_mat<K>(S, ux, t0);
+        line_mat<K>(DS, ux, t1);
+        kl_store<K>(A, pos[0], t0);  // S_x u
+        kl_store<K>(B, pos[0], t1);  // DS_x u
+      }
+      sync();
+      if (vol) {
+        kl_load<K>(A, pos[1], t0);
+        line_mat<K>(S, t0, t1);
+        line_mat<K>(DS, t0, t2);
+        kl_store<K>(A, pos[1], t1);   // S_y S_x u
+        kl_store<K>(Cc, pos[1], t2);  // DS_y S_x u
+        kl_load<K>(B, pos[1], t0);
+        line_mat<K>(S, t0, t1);
+        kl_store<K>(B, pos[1], t1);   // S_y DS_x u
+      }
+      sync();
+      if (vol) {
+        // this lane's z-line: Gauss indices (q0, q1) = (l % K, l / K)
+        const int q0 = l % K, q1 = l / K;
+        kl_load<K>(A, pos[2], t0);
+        line_mat<K>(DS, t0, t3);      // d/dz
+        kl_load<K>(Cc, pos[2], t0);
+        line_mat<K>(S, t0, t2);       // d/dy
+        kl_load<K>(B, pos[2], t0);
+        line_mat<K>(S, t0, t1);       // d/dx
+        const int64_t kb = a.seg[0] + (int64_t)ci * ND + q0 + K * q1;
+        const T w01 = a.hs * Wg[q0] * Wg[q1];
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          T cq = w01 * Wg[m];
+          if (a.kappa) cq *= a.kappa[kb + K * K * m];
+          t1[m] *= cq;
+          t2[m] *= cq;
+          t3[m] *= cq;
+        }
+        line_matT<K>(S, t1, t0);
+        kl_store<K>(A, pos[2], t0);
+        line_matT<K>(S, t2, t0);
+        kl_store<K>(Cc, pos[2], t0);
+        line_matT<K>(DS, t3, t0);
+        kl_store<K>(B, pos[2], t0);
+      }
+      sync();
+      if (vol) {
+        kl_load<K>(A, pos[1], t0);
+        line_matT<K>(S, t0, t1);
+        kl_store<K>(A, pos[1], t1);   // S_y^T (x-part)
+        kl_load<K>(Cc, pos[1], t0);
+        line_matT<K>(DS, t0, t1);
+        kl_load<K>(B, pos[1], t0);
+        line_matT<K>(S, t0, t2);
+#pragma unroll
+        for (int q = 0; q < K; ++q) t1[q] += t2[q];
+        kl_store<K>(B, pos[1], t1);   // DS_y^T (y-part) + S_y^T (z-part)
+      }
+      sync();
+      if (vol) {
+        kl_load<K>(A, pos[0], t0);
+        line_matT<K>(DS, t0, t1);
+        kl_load<K>(B, pos[0], t0);
+        line_matT<K>(S, t0, t2);
+#pragma unroll
+        for (int q = 0; q < K; ++q) t1[q] += t2[q];
+        kl_store<K>(OUT, pos[0], t1);
+      }
+      sync();
+    } else {
+      if (vol) {
+        line_mat<K>(S, ux, t0);
+        line_mat<K>(DS, ux, t1);
+        kl_store<K>(A, pos[0], t0);  // S_x u
+        kl_store<K>(B, pos[0], t1);  // DS_x u
+      }
+      sync();
+      if (vol) {
+        // this lane's y-line: Gauss index q0 = l
+        kl_load<K>(A, pos[1], t0);
+        line_mat<K>(DS, t0, t2);      // d/dy
+        kl_load<K>(B, pos[1], t0);
+        line_mat<K>(S, t0, t1);       // d/dx
+        const int64_t kb = a.seg[0] + (int64_t)ci * ND + l;
+        const T w0 = a.hs * Wg[l];
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          T cq = w0 * Wg[m];
+          if (a.kappa) cq *= a.kappa[kb + K * m];
+          t1[m] *= cq;
+          t2[m] *= cq;
+        }
+        line_matT<K>(S, t1, t0);
+        kl_store<K>(A, pos[1], t0);
+        line_matT<K>(DS, t2, t0);
+        kl_store<K>(B, pos[1], t0);
+      }
+      sync();
+      if (vol) {
+        kl_load<K>(A, pos[0], t0);
+        line_matT<K>(DS, t0, t1);
+        kl_load<K>(B, pos[0], t0);
+        line_matT<K>(S, t0, t2);
+#pragma unroll
+        for (int q = 0; q < K; ++q) t1[q] += t2[q];
+        kl_store<K>(OUT, pos[0], t1);
+      }
+      sync();
+    }
+    // ---- faces, one normal axis at a time; lane l is face node / Gauss
+    // point l of the face (lower in-face axis fastest)
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      T R[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) R[q] = 0;
+      T uo[K];
+      if (valid) kl_load<K>(U, pos[ax], uo);
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int s = 2 * ax + side;
+        // wave-uniform loop bounds: every lane takes part in the syncs
+        const bool fs = valid && sipg_on && ((fl >> (kFlagStr + s)) & 1);
+        const bool fg = valid && gp_on && ((fl >> (kFlagGP + s)) & 1);
+        const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
+        const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
+        const T sigma = side ? T(1) : T(-1);
+        const T* un = nb[s];
+        // ghost penalty: derivative jumps of every order, exact in-face mass
+        // (skipped by waves without such a face on this slot)
+        if (__any(fg)) {
+          if (fg) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+              T dj = 0;
+#pragma unroll
+              for (int q = 0; q < K; ++q) dj += Eo[j * K + q] * uo[q] - En[j * K + q] * un[q];
+              W.FJ[cc][j][l] = dj;
+            }
+          }
+          sync();
+          if (fg) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+              const T g = a.hs * GW[j] * face_transform<K, D, false>(M, W.FJ[cc][j], l);
+#pragma unroll
+              for (int q = 0; q < K; ++q) R[q] += Eo[j * K + q] * g;
+            }
+          }
+          sync();
+        }
+        if (!__any(fs)) continue;
+        // SIPG with kappa at the face Gauss points
+        if (fs) {
+          T ov = 0, od = 0, nv = 0, nd = 0;
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            ov += Eo[q] * uo[q];
+            od += Eo[K + q] * uo[q];
+            nv += En[q] * un[q];
+            nd += En[K + q] * un[q];
+          }
+          W.F0[cc][l] = sigma * (ov - nv);
+          W.F1[cc][l] = T(0.5) * (od + nd);
+        }
+        sync();
+        T fv = 0, fd = 0;
+        if (fs) {
+          const T J = face_transform<K, D, false>(S, W.F0[cc], l);
+          const T Av = face_transform<K, D, false>(S, W.F1[cc], l);
+          const int q0 = l % K, q1 = D == 3 ? l / K : 0;
+          T cq = a.hs * Wg[q0] * (D == 3 ? Wg[q1] : T(1));
+          if (a.kappa) cq *= a.kappa[fko[s] + l];
+          fv = cq * sigma * (a.gamma * J - Av);
+          fd = T(-0.5) * cq * J;
+        }
+        sync();
+        if (fs) {
+          W.F0[cc][l] = fv;
+          W.F1[cc][l] = fd;
+        }
+        sync();
+        if (fs) {
+          const T gv = face_transform<K, D, true>(S, W.F0[cc], l);
+          const T gd = face_transform<K, D, true>(S, W.F1[cc], l);
+#pragma unroll
+          for (int q = 0; q < K; ++q) R[q] += Eo[q] * gv + Eo[K + q] * gd;
+        }
+        sync();
+      }
+      if (valid) {
+        kl_load<K>(OUT, pos[ax], t0);
+#pragma unroll
+        for (int q = 0; q < K; ++q) t0[q] += R[q];
+        kl_store<K>(OUT, pos[ax], t0);
+      }
+      sync();
+    }
+    if (valid) {
+      kl_load<K>(OUT, pos[0], t0);
+      T* out = v + (int64_t)r * ND;
+#pragma unroll
+      for (int q = 0; q < K; ++q) out[bx + q] = t0[q];
+    }
+    sync();
+  }
+}
+
 // ------------------------------------------------ cut cells, point lines
 // One wave per cut cell.  The structured faces of the cell (SIPG on faces
 // inside the domain, ghost penalty) use the Kronecker face pipeline of the
@@ -2170,7 +2504,11 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
       if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
     } else {
-      if (gi > 0) inside_kernel<K, D, T, false><<<gi, NT, 0, s>>>(a, x, y, v, dk);
+      constexpr int CW = KronShape<K, D>::C;
+      const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
+      if (gk > 0)
+        kappa_struct_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.kface_inside,
+                                                                        a.n_inside, 1);
     }
     {
       // structured faces and ghost penalty of the cut cells (overwrites
@@ -2182,8 +2520,9 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       if (gs > 0) {
         if (a.kappa == nullptr)
           inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
-        else if (gc > 0)
-          cut_kernel<K, D, T, false><<<gc, NT, 0, s>>>(a, x, y, v, dk);
+        else
+          kappa_struct_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.kface_cut, a.n_cut,
+                                                                          0);
       }
       if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
         static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
