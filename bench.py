@@ -194,6 +194,11 @@ def solve_mode(args, wl, rng, plan, op, t_setup):
     r = op.apply(u)
     resdc = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
     err = float(torch.linalg.norm(u - ustar) / torch.linalg.norm(ustar))
+    # one adjoint pass at the solution: A^T w and dL/dkappa for w = A u - b
+    w = (r - b).contiguous()
+    atw = torch.empty_like(w)
+    dk = torch.empty(plan.info["n_qp"], dtype=torch.float64, device=w.device)
+    (_, tadj) = timed(lambda: op.apply_adjoint(w, u, atw, dk), ops)
     out = {
         "metric": "solve time to 1e-10 relative residual, FP64 CG vs FP32-inner defect correction",
         "value": t64 / tdc,
@@ -210,6 +215,7 @@ def solve_mode(args, wl, rng, plan, op, t_setup):
                               "rel_residual": resdc, "converged": idc["converged"], "history": idc["history"],
                               "inner_rtol": args.inner_rtol},
         "solution_rel_error": err,
+        "adjoint_at_solution_s": tadj,
         "setup_s": t_setup,
         "kernel_hash": kernel_hash(),
     }
