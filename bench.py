@@ -176,21 +176,18 @@ def solve_mode(args, wl, rng, plan, op, t_setup):
     import torch
 
     import ufem_inputs as ui
-    from paper_2404_07911_amd.solvers import DeviceOps, cg, defect_correction, timed
+    from paper_2404_07911_amd.solvers import DeviceOps, device_cg, device_defect_correction, timed
 
     ops = DeviceOps(0)
     n = plan.info["n_dofs"]
     ustar = torch.from_numpy(ui.uniform_vector(rng, n)).cuda()
     b = op.apply(ustar)
 
-    def a(x, out):
-        op.apply(x, out)
-
     x = torch.zeros_like(b)
-    (x, i64), t64 = timed(lambda: cg(a, b, x, ops, rtol=args.tol, maxiter=200000), ops)
+    (x, i64), t64 = timed(lambda: device_cg(op, b, x, rtol=args.tol, maxiter=400000), ops)
     r = op.apply(x)
     res64 = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
-    (u, idc), tdc = timed(lambda: defect_correction(a, a, b, ops, tol=args.tol, inner_rtol=args.inner_rtol), ops)
+    (u, idc), tdc = timed(lambda: device_defect_correction(op, b, tol=args.tol, inner_rtol=args.inner_rtol), ops)
     r = op.apply(u)
     resdc = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
     err = float(torch.linalg.norm(u - ustar) / torch.linalg.norm(ustar))

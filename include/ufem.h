@@ -193,6 +193,22 @@ int ufem_dot(int32_t precision, int64_t n, const void* x, const void* y, double*
 int ufem_axpby(int32_t precision, int64_t n, double a, const void* x, double b, void* y, void* stream);
 int ufem_cast(int32_t precision_in, int32_t precision_out, int64_t n, const void* x, void* y, void* stream);
 
+/* n_iter iterations of unpreconditioned conjugate gradients for A x = b
+ * (the paper solves with CG, Section 3.6), entirely on the device: each
+ * iteration is one apply (Ap) and three vector kernels, with no host
+ * synchronisation.  x, r, p, ap: device, n_dofs values of `precision`, no
+ * two overlapping; scal: device, 4 float64 values.  On entry r = b - A x,
+ * p = r, scal = [r.r, 0, 0, 0] (the caller sets them up, e.g. with
+ * ufem_apply / ufem_axpby / ufem_dot); on return x, r, p are advanced by
+ * n_iter iterations, scal[0] = r.r of the new residual, and scal[3] != 0 if
+ * p.Ap <= 0 occurred (breakdown: x, r, p were left as they were before that
+ * iteration and further iterations do nothing).  The dot products
+ * accumulate in float64 for both precisions, so their rounding order (one
+ * atomic add per block) varies between runs.  Asynchronous on `stream`;
+ * allocates nothing. */
+int ufem_cg_iterate(ufem_op* op, int32_t precision, int32_t n_iter, void* x, void* r, void* p, void* ap,
+                    double* scal, void* stream);
+
 /* Thread-local message of the last failing call (never NULL). */
 const char* ufem_last_error(void);
 

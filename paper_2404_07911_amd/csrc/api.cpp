@@ -721,6 +721,38 @@ int ufem_apply_adjoint(ufem_op* op, int32_t precision, const void* w, const void
   return UFEM_OK;
 }
 
+int ufem_cg_iterate(ufem_op* op, int32_t precision, int32_t n_iter, void* x, void* r, void* p, void* ap, double* scal,
+                    void* stream) {
+  if (!op || !x || !r || !p || !ap || !scal) return fail(UFEM_EINVAL, "ufem_cg_iterate: null argument");
+  if (n_iter < 0) return fail(UFEM_EINVAL, "ufem_cg_iterate: n_iter < 0");
+  if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_cg_iterate: bad precision");
+  const size_t bytes = (size_t)op->P.n_dofs() * (precision == UFEM_F64 ? 8 : 4);
+  const void* vec[4] = {x, r, p, ap};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (overlap(vec[i], vec[j], bytes)) return fail(UFEM_EINVAL, "ufem_cg_iterate: vectors overlap");
+  for (int i = 0; i < 4; ++i)
+    if (overlap2(scal, 4 * sizeof(double), vec[i], bytes)) return fail(UFEM_EINVAL, "ufem_cg_iterate: scal overlaps a vector");
+  DeviceGuard g(op->device);
+  const int64_t n = op->P.n_dofs();
+  for (int it = 0; it < n_iter; ++it) {
+    hipError_t e;
+    if (precision == UFEM_F64) {
+      auto a = op->args<double>(op->prec[0]);
+      e = ufem::launch_operator<double>(a, op->P.dim, op->P.p, (const double*)p, (double*)ap, nullptr, nullptr, false,
+                                        (hipStream_t)stream);
+    } else {
+      auto a = op->args<float>(op->prec[1]);
+      e = ufem::launch_operator<float>(a, op->P.dim, op->P.p, (const float*)p, (float*)ap, nullptr, nullptr, false,
+                                       (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate: apply");
+    e = ufem::launch_cg_tail(precision, n, x, r, p, ap, scal, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate: vector update");
+  }
+  return UFEM_OK;
+}
+
 int ufem_dot(int32_t precision, int64_t n, const void* x, const void* y, double* out, void* stream) {
   if (!x || !y || !out || n < 0) return fail(UFEM_EINVAL, "ufem_dot: bad argument");
   if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_dot: bad precision");

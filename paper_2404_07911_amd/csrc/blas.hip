@@ -47,7 +47,80 @@ __global__ void __launch_bounds__(256) zero_kernel(int64_t n, T* __restrict__ y)
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
+// ------------------------------------------------- conjugate gradients
+// Device-resident CG: the scalars live in device memory, scal = [r.r, p.Ap,
+// new r.r, breakdown flag]; p.Ap and the new r.r are accumulated in FP64 by
+// block sums and one atomic add per block, and cleared again by cg_roll.
+__device__ __forceinline__ double block_sum(double s) {
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// x += alpha p, r -= alpha Ap, new r.r; alpha = r.r / p.Ap
+template <typename T>
+__global__ void __launch_bounds__(256) cg_update_kernel(int64_t n, T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p, const T* __restrict__ ap,
+                                                        double* __restrict__ scal) {
+  const double pap = scal[1];
+  if (scal[3] != 0.0 || !(pap > 0.0)) return;
+  const T alpha = (T)(scal[0] / pap);
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const T ri = r[i] - alpha * ap[i];
+    r[i] = ri;
+    s += (double)ri * (double)ri;
+  }
+  const double bs = block_sum(s);
+  if (threadIdx.x == 0) atomicAdd(scal + 2, bs);
+}
+
+// p = r + beta p, beta = new r.r / r.r
+template <typename T>
+__global__ void __launch_bounds__(256) cg_direction_kernel(int64_t n, const T* __restrict__ r, T* __restrict__ p,
+                                                           const double* __restrict__ scal) {
+  if (scal[3] != 0.0 || !(scal[1] > 0.0)) return;
+  const T beta = (T)(scal[2] / scal[0]);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = r[i] + beta * p[i];
+}
+
+// next iteration's scalars (one thread); a non-positive p.Ap stops the loop
+__global__ void cg_roll_kernel(double* scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (scal[3] == 0.0) {
+    if (!(scal[1] > 0.0)) scal[3] = 1.0;
+    else scal[0] = scal[2];
+  }
+  scal[1] = 0.0;
+  scal[2] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const void* ap, double* scal, hipStream_t s) {
+  const int g = grid_for(n);
+  if (n > 0) {
+    if (prec == 0) {
+      dot_kernel<double><<<g, 256, 0, s>>>(n, (const double*)p, (const double*)ap, scal + 1);
+      cg_update_kernel<double><<<g, 256, 0, s>>>(n, (double*)x, (double*)r, (const double*)p, (const double*)ap, scal);
+      cg_direction_kernel<double><<<g, 256, 0, s>>>(n, (const double*)r, (double*)p, scal);
+    } else {
+      dot_kernel<float><<<g, 256, 0, s>>>(n, (const float*)p, (const float*)ap, scal + 1);
+      cg_update_kernel<float><<<g, 256, 0, s>>>(n, (float*)x, (float*)r, (const float*)p, (const float*)ap, scal);
+      cg_direction_kernel<float><<<g, 256, 0, s>>>(n, (const float*)r, (float*)p, scal);
+    }
+  }
+  cg_roll_kernel<<<1, 64, 0, s>>>(scal);
+  return hipGetLastError();
+}
+
 
 template <typename T>
 hipError_t launch_operator(const DevArgs<T>& a, int dim, int degree, const T* u, T* v, const T* w_adj, T* dkappa,

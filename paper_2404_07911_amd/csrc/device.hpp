@@ -135,6 +135,8 @@ template <typename T>
 hipError_t launch_operator(const DevArgs<T>& a, int dim, int degree, const T* u, T* v, const T* w_adj, T* dkappa,
                            bool adjoint, hipStream_t s);
 
+hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const void* ap, double* scal,
+                           hipStream_t s);
 hipError_t launch_dot(int prec, int64_t n, const void* x, const void* y, double* out, hipStream_t s);
 hipError_t launch_axpby(int prec, int64_t n, double a, const void* x, double b, void* y, hipStream_t s);
 hipError_t launch_cast(int pin, int pout, int64_t n, const void* x, void* y, hipStream_t s);

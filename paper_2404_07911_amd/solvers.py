@@ -206,6 +206,99 @@ def defect_correction(apply64, apply32, b, ops, tol=1e-10, inner_rtol=1e-4, max_
     return u, info
 
 
+def device_cg(op, b, x, rtol=1e-10, maxiter=100000, chunk=32, rnorm0=None):
+    """CG for op's matrix with every iteration on the device
+    (`ufem_cg_iterate`): the host reads the residual norm once per `chunk`
+    iterations, so up to chunk - 1 iterations beyond the target may run.
+    b, x: device tensors of one precision (x updated in place).  Returns
+    (x, info) like `cg`."""
+    import torch
+
+    ops = DeviceOps(b.device.index or 0)
+    prec = ops._prec(b)
+    r = torch.empty_like(b)
+    op.apply(x, r)
+    ops.axpby(1.0, b, -1.0, r)  # r = b - A x
+    p = r.clone()
+    ap = torch.empty_like(b)
+    scal = torch.zeros(4, dtype=torch.float64, device=b.device)
+    L.check(L.lib().ufem_dot(prec, r.numel(), C.c_void_p(r.data_ptr()), C.c_void_p(r.data_ptr()),
+                             C.c_void_p(scal.data_ptr()), ops._stream()))
+    bnorm = math.sqrt(ops.dot(b, b)) if rnorm0 is None else rnorm0
+    info = {"iterations": 0, "converged": False, "breakdown": False, "rel_residual": None}
+    if bnorm == 0.0:
+        info.update(converged=True, rel_residual=0.0)
+        return x, info
+    target = (rtol * bnorm) ** 2
+    it = 0
+    rr = float(scal[0].item())
+    while rr > target and it < maxiter:
+        n = min(chunk, maxiter - it)
+        L.check(L.lib().ufem_cg_iterate(op._h, prec, n, C.c_void_p(x.data_ptr()), C.c_void_p(r.data_ptr()),
+                                        C.c_void_p(p.data_ptr()), C.c_void_p(ap.data_ptr()),
+                                        C.c_void_p(scal.data_ptr()), ops._stream()))
+        it += n
+        sc = scal.cpu()
+        rr = float(sc[0])
+        if sc[3] != 0.0:
+            info["breakdown"] = True
+            break
+    info["iterations"] = it
+    info["rel_residual"] = math.sqrt(max(rr, 0.0)) / bnorm
+    info["converged"] = rr <= target
+    return x, info
+
+
+def device_defect_correction(op, b, tol=1e-10, inner_rtol=1e-4, max_outer=60, max_inner=100000, chunk=32,
+                             stagnation_factor=0.5, stagnation_window=3):
+    """`defect_correction` with the FP32 inner solves done by `device_cg`
+    (b: float64 device tensor); an inner solve stops at inner_rtol or, when
+    less is needed to reach tol, at 0.3 tol ||b|| / ||r|| (at most 1e-2).
+    Returns (u, info) like `defect_correction`."""
+    import torch
+
+    ops = DeviceOps(b.device.index or 0)
+    u = torch.zeros_like(b)
+    r = b.clone()
+    bnorm = math.sqrt(ops.dot(b, b))
+    hist = []
+    inner_total = 0
+    info = {"outer": 0, "inner_iterations": 0, "converged": False, "stagnated": False, "history": hist,
+            "inner_breakdown": False}
+    if bnorm == 0.0:
+        info["converged"] = True
+        return u, info
+    r32 = torch.empty(b.numel(), dtype=torch.float32, device=b.device)
+    d64 = torch.empty_like(b)
+    for k in range(max_outer + 1):
+        rnorm = math.sqrt(ops.dot(r, r))
+        hist.append(rnorm / bnorm)
+        if rnorm <= tol * bnorm:
+            info["converged"] = True
+            break
+        if len(hist) > stagnation_window and hist[-1] > stagnation_factor * hist[-1 - stagnation_window]:
+            info["stagnated"] = True
+            break
+        if k == max_outer:
+            break
+        ops.copy(r32, r)
+        ops.axpby(0.0, r32, 1.0 / rnorm, r32)  # r32 = r / ||r||
+        d32 = torch.zeros_like(r32)
+        # the last correction only has to close the remaining gap to tol
+        rtol_k = min(1e-2, max(inner_rtol, 0.3 * tol * bnorm / rnorm))
+        _, ii = device_cg(op, r32, d32, rtol=rtol_k, maxiter=max_inner, chunk=chunk, rnorm0=1.0)
+        inner_total += ii["iterations"]
+        info["inner_breakdown"] |= ii["breakdown"]
+        ops.copy(d64, d32)
+        ops.axpby(rnorm, d64, 1.0, u)  # u += ||r|| d
+        op.apply(u, r)
+        ops.axpby(1.0, b, -1.0, r)  # r = b - A u
+        info["outer"] = k + 1
+    info["inner_iterations"] = inner_total
+    info["rel_residual"] = hist[-1]
+    return u, info
+
+
 def timed(fn, ops):
     ops.sync()
     t0 = time.perf_counter()

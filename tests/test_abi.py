@@ -109,6 +109,8 @@ def test_null_arguments_are_rejected():
     assert lib.ufem_axpby(0, 10, 1.0, None, 1.0, None, None) == L.UFEM_EINVAL
     assert lib.ufem_cast(0, 1, 10, None, None, None) == L.UFEM_EINVAL
     assert lib.ufem_cast(0, 2, 10, C.c_void_p(16), C.c_void_p(4096), None) == L.UFEM_EINVAL
+    assert lib.ufem_cg_iterate(None, 0, 1, None, None, None, None, None, None) == L.UFEM_EINVAL
+    assert lib.ufem_apply_part(None, 0, 15, None, None, None) == L.UFEM_EINVAL
     assert b"ufem_" in lib.ufem_last_error()
 
 

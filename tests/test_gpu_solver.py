@@ -67,6 +67,54 @@ def test_defect_correction_and_fp64_cg(torch, ball):
     assert res64 < 2e-10, res64
 
 
+def test_device_cg_and_defect_correction(torch, ball):
+    """The device-resident CG (every iteration on the GPU) and the defect
+    correction built on it reach 1e-10, checked with the oracle; the FP32
+    inner solve is a device CG in FP32."""
+    from paper_2404_07911_amd.solvers import device_cg, device_defect_correction
+
+    wl, ora, op, ustar = ball
+    us = torch.from_numpy(ustar).cuda()
+    b = op.apply(us)
+    bh = b.cpu().numpy()
+    _say("[solve] device cg fp64")
+    x = torch.zeros_like(b)
+    x, info = device_cg(op, b, x, rtol=1e-10, maxiter=20000, chunk=16)
+    assert info["converged"] and not info["breakdown"], info
+    res = np.linalg.norm(bh - ora.apply(x.cpu().numpy())) / np.linalg.norm(bh)
+    assert res < 2e-10, res
+    _say("[solve] device defect correction")
+    u, info = device_defect_correction(op, b, tol=1e-10, inner_rtol=1e-4)
+    assert info["converged"], info
+    assert info["outer"] >= 2
+    res = np.linalg.norm(bh - ora.apply(u.cpu().numpy())) / np.linalg.norm(bh)
+    assert res < 2e-10, res
+
+
+def test_device_cg_breakdown_flag(torch, ball):
+    """A right-hand side of zero leaves x at zero (converged at once); an
+    operator that is not positive definite along p raises the breakdown flag:
+    here the search direction is set to zero by hand (p.Ap = 0)."""
+    import ctypes as C
+
+    from paper_2404_07911_amd import _lib as L
+
+    wl, ora, op, ustar = ball
+    n = ora.n_dofs
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    r = torch.ones(n, dtype=torch.float64, device="cuda")
+    p = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ap = torch.empty_like(p)
+    scal = torch.tensor([float(n), 0.0, 0.0, 0.0], dtype=torch.float64, device="cuda")
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L.check(L.lib().ufem_cg_iterate(op._h, L.F64, 3, C.c_void_p(x.data_ptr()), C.c_void_p(r.data_ptr()),
+                                    C.c_void_p(p.data_ptr()), C.c_void_p(ap.data_ptr()), C.c_void_p(scal.data_ptr()),
+                                    s))
+    sc = scal.cpu().numpy()
+    assert sc[3] != 0.0 and sc[0] == float(n)
+    assert float(x.abs().max()) == 0.0 and float((r - 1).abs().max()) == 0.0
+
+
 def test_autograd_matches_oracle_gradients(torch, ball):
     from paper_2404_07911_amd import ufem_apply
 
