@@ -1750,6 +1750,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
     // (indices clamped into the batch, so that the loads need no guard)
 #pragma unroll
     for (int it = 0; it < (ME * ND + NT - 1) / NT; ++it) {
+      if (NT * it >= ne * ND) break;  // uniform
       const int idx = min(t + NT * it, ne * ND - 1);
       const int e = idx / ND, l = idx % ND;
       const int64_t ro = (int64_t)ent[4 * e] * ND + l;
@@ -1777,7 +1778,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
           else if constexpr (D == 3) line_work_cell<K, D, 2>(a.tab, a, info, hd.x, L, Uo, W.REC, t);
         }
       }
-      if (!done) {
+      if (g < total && !done) {  // a line of a switched-off term (records past total are not read)
 #pragma unroll
         for (int c = 0; c < RS; ++c) W.REC[t * LineShape<K, D>::RSP + c] = 0;
       }
@@ -2035,10 +2036,7 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
         const int info = hd.y & 0xffffff, e = hd.y >> 24;
         const int slot = ent[4 * e + 2] >> kBatchOffsetBits;
         line_work_face<K, D, RP>(a.tab, a, info, hd.x, slot, L, W.TR[e], W.REC, t);
-      } else {
-#pragma unroll
-        for (int c = 0; c < RS; ++c) W.REC[c * RP + t] = 0;
-      }
+      }  // (records past total are not read)
       sync();
       const int r1 = min(total, base + NT);
       int c = -1, prev = -1;
