@@ -2454,6 +2454,122 @@ __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __res
   }
 }
 
+// cut faces, dL/dkappa: per face entry whose cell is the face's lower cell
+// (each point written once), the value and normal-derivative traces of w and
+// u on both sides on the face-node grid (as in cut_face_kernel), then per
+// line the in-face contraction, per point the SIPG integrand of (w, u)
+template <int K, int D, typename T>
+struct FaceDkWork {
+  static constexpr int NF = ipow(K, D - 1), ME = batch_max_entries(ipow(K, D), true);
+  T TR[ME][8][NF];  // w: own value, own d_n, nbr value, nbr d_n; then u
+  int rec[batch_record_ints(ME)];
+};
+
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(64) cut_face_dk_kernel(DevArgs<T> a, const T* __restrict__ w,
+                                                         const T* __restrict__ u, T* __restrict__ dk,
+                                                         const int32_t* __restrict__ brec,
+                                                         const int32_t* __restrict__ desc, int n_batches) {
+  using FW = FaceDkWork<K, D, T>;
+  constexpr int ND = ipow(K, D), NF = FW::NF, ME = FW::ME, NT = kBatchLines, NR = batch_record_ints(ME);
+  __shared__ FW W;
+  const T* tab = a.tab;
+  const T* Xn = tab + TabOff::X(K);
+  const T* ID = tab + TabOff::ID(K);
+  const int t = threadIdx.x;
+  for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
+    if (t < NR) W.rec[t] = brec[(int64_t)b * NR + t];
+    sync();
+    const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
+    const int* ent = W.rec + 4;
+#pragma unroll
+    for (int it = 0; it < (ME * NF + NT - 1) / NT; ++it) {
+      if (NT * it >= ne * NF) break;  // uniform
+      const int idx = min(t + NT * it, ne * NF - 1);
+      const int e = idx / NF, o = idx % NF;
+      const int sl = ent[4 * e + 2] >> kBatchOffsetBits, N = sl >> 1;
+      const int ia = o / (D == 3 ? K : 1), ib = D == 3 ? o % K : 0;
+      int sN, off;
+      if constexpr (D == 3) {
+        sN = N == 0 ? 1 : (N == 1 ? K : K * K);
+        off = N == 0 ? ia * K + ib * K * K : (N == 1 ? ia + ib * K * K : ia + ib * K);
+      } else {
+        sN = N == 0 ? 1 : K;
+        off = N == 0 ? ia * K : ia;
+      }
+      const T* Eo = tab + ((sl & 1) ? TabOff::E1(K) : TabOff::E0(K));
+      const T* En = tab + ((sl & 1) ? TabOff::E0(K) : TabOff::E1(K));
+      const int64_t ro = (int64_t)ent[4 * e] * ND + off, rn = (int64_t)ent[4 * e + 3] * ND + off;
+#pragma unroll
+      for (int fld = 0; fld < 2; ++fld) {
+        const T* src = fld ? u : w;
+        T o0 = 0, o1 = 0, n0 = 0, n1 = 0;
+#pragma unroll
+        for (int nn = 0; nn < K; ++nn) {
+          const T a0 = src[ro + nn * sN], b0 = src[rn + nn * sN];
+          o0 += Eo[nn] * a0;
+          o1 += Eo[K + nn] * a0;
+          n0 += En[nn] * b0;
+          n1 += En[K + nn] * b0;
+        }
+        W.TR[e][4 * fld][o] = o0;
+        W.TR[e][4 * fld + 1][o] = o1;
+        W.TR[e][4 * fld + 2][o] = n0;
+        W.TR[e][4 * fld + 3][o] = n1;
+      }
+    }
+    sync();
+    for (int g = t; g < total; g += NT) {
+      const int2 hd = g < kBatchLines ? *reinterpret_cast<const int2*>(desc + 2 * ((int64_t)b * kBatchLines + g))
+                                      : batch_desc(desc, n_batches, ovf, g);
+      const int info = hd.y & 0xffffff, e = hd.y >> 24;
+      const int slot = ent[4 * e + 2] >> kBatchOffsetBits;
+      if ((slot & 1) == 0) continue;  // the face's upper cell: its lower cell writes
+      const int n = info & 0xffff, p0 = hd.x;
+      const bool alongB = ((info >> 16) & 0xf) == 1;
+      const int fk = alongB ? 1 : 0;
+      const int64_t stride = a.n_fcut;
+      T F[K], dF[K];
+      if constexpr (D == 3) {
+        lagrange1d<K>(Xn, ID, a.fcut_x[(1 - fk) * stride + p0], F, dF);
+      } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) F[i] = 1;
+      }
+      T col[8][K];
+#pragma unroll
+      for (int lk = 0; lk < K; ++lk) {
+#pragma unroll
+        for (int k8 = 0; k8 < 8; ++k8) col[k8][lk] = 0;
+#pragma unroll
+        for (int f = 0; f < (D == 3 ? K : 1); ++f) {
+          const int o = D == 3 ? (alongB ? lk + f * K : lk * K + f) : lk;
+#pragma unroll
+          for (int k8 = 0; k8 < 8; ++k8) col[k8][lk] += F[f] * W.TR[e][k8][o];
+        }
+      }
+      for (int pi = 0; pi < n; ++pi) {
+        const int64_t q = p0 + pi;
+        T Z[K], dZ[K];
+        lagrange1d<K>(Xn, ID, a.fcut_x[fk * stride + q], Z, dZ);
+        T ev[8];
+#pragma unroll
+        for (int k8 = 0; k8 < 8; ++k8) {
+          T sacc = 0;
+#pragma unroll
+          for (int ii = 0; ii < K; ++ii) sacc += Z[ii] * col[k8][ii];
+          ev[k8] = sacc;
+        }
+        // the lower cell: jump = own - neighbour, average of the d_n
+        const T Jw = ev[0] - ev[2], Aw = T(0.5) * (ev[1] + ev[3]);
+        const T Ju = ev[4] - ev[6], Au = T(0.5) * (ev[5] + ev[7]);
+        dk[a.seg[3] + q] = a.hs * a.fcut_w[q] * (-Aw * Ju - Jw * Au + a.gamma * Jw * Ju);
+      }
+    }
+    sync();
+  }
+}
+
 // resident workgroups of a kernel per compute unit (persistent grids)
 template <typename Kern>
 int blocks_per_cu(Kern kernel) {
@@ -2484,8 +2600,8 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
         cut_dk_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.vbrec, a.vdesc,
                                                                                    a.n_vbatch);
       if (a.n_fbatch > 0)
-        cut_dk_kernel<K, D, T, true><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.fbrec, a.fdesc,
-                                                                                  a.n_fbatch);
+        cut_face_dk_kernel<K, D, T><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.fbrec, a.fdesc,
+                                                                                 a.n_fbatch);
     }
     return hipGetLastError();
   }
