@@ -179,6 +179,8 @@ int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u,
  *   dkappa[q] := a_q(w, u), the contribution of quadrature point q to
  *                w^T A(kappa) u divided by kappa_q (dL/dkappa_q for
  *                L = 0.5 |A u - b|^2 with w = A u - b).
+ * The term mask (ufem_set_terms) selects the terms of ATw; dkappa always
+ * covers every kappa-weighted term (volume, SIPG and Nitsche points).
  * w, u, ATw: device, n_dofs; dkappa: device, n_qp, or NULL to skip.  ATw must
  * not overlap w or u. */
 int ufem_apply_adjoint(ufem_op* op, int32_t precision, const void* w, const void* u, void* ATw,

@@ -116,13 +116,10 @@ struct ufem_op {
   int64_t bytes = 0;
   int64_t max_bytes = 0;
   // integer data
-  int32_t *inside = nullptr, *cut_order = nullptr, *cut_rank = nullptr, *nb = nullptr, *flags = nullptr,
-          *slot_face = nullptr, *face_qn = nullptr;
-  int64_t *face_qoff = nullptr, *vol_off = nullptr, *surf_off = nullptr, *kface_inside = nullptr,
-          *kface_cut = nullptr;
-  int32_t *cell_line_off = nullptr, *face_lbeg = nullptr, *face_lend = nullptr, *line_first = nullptr,
-          *line_info = nullptr, *cell_desc = nullptr, *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr,
-          *fdesc = nullptr, *kinfo_inside = nullptr, *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
+  int32_t* inside = nullptr;
+  int64_t *kface_inside = nullptr, *kface_cut = nullptr;
+  int32_t *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr, *fdesc = nullptr, *kinfo_inside = nullptr,
+          *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   // per-precision data
   struct Prec {
@@ -198,19 +195,6 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.n_inside = (int32_t)P.inside.size();
   a.n_cut = (int32_t)P.cut.size();
   a.inside = inside;
-  a.cut_order = cut_order;
-  a.cut_rank = cut_rank;
-  a.nb = nb;
-  a.flags = flags;
-  a.slot_face = slot_face;
-  a.face_qoff = face_qoff;
-  a.face_qn = face_qn;
-  a.cell_line_off = cell_line_off;
-  a.face_lbeg = face_lbeg;
-  a.face_lend = face_lend;
-  a.line_first = line_first;
-  a.line_info = line_info;
-  a.cell_desc = cell_desc;
   a.kinfo_inside = kinfo_inside;
   a.kinfo_cut = kinfo_cut;
   a.kinfo_all = kinfo_all;
@@ -227,8 +211,6 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.sf_bp = sf_bp;
   a.sf_ax = sf_ax;
   a.n_sfaces = n_sfaces;
-  a.vol_off = vol_off;
-  a.surf_off = surf_off;
   a.vol_x = (const T*)d.vol_x;
   a.vol_w = (const T*)d.vol_w;
   a.surf_x = (const T*)d.surf_x;
@@ -395,7 +377,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     const int dim = P.dim, S = 2 * dim;
     const size_t na = P.active.size();
     // neighbour ranks and flags per active cell and slot
-    std::vector<int32_t> nb(na * S, -1), flags(na, 0), slot_face(P.slot_face);
+    std::vector<int32_t> nb(na * S, -1), flags(na, 0);
     for (size_t r = 0; r < na; ++r) {
       for (int s = 0; s < S; ++s) {
         int32_t fi = P.slot_face[r * S + s];
@@ -407,14 +389,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         if (f.kind == ufem::kFaceCut) flags[r] |= 1 << (ufem::kFlagCut + s);
       }
     }
-    std::vector<int64_t> face_qoff(P.faces.size());
-    std::vector<int32_t> face_qn(P.faces.size());
-    for (size_t i = 0; i < P.faces.size(); ++i) {
-      face_qoff[i] = P.faces[i].qp_off;
-      face_qn[i] = P.faces[i].qp_n;
-    }
     // point lines
-    std::vector<int32_t> cloff(P.cell_line_off.begin(), P.cell_line_off.end());
     std::vector<int32_t> flb(P.faces.size(), 0), fle(P.faces.size(), 0), linfo(P.line_first.size());
     for (size_t i = 0; i + 1 < P.face_line_off.size(); ++i) {
       flb[P.fcut_face[i]] = (int32_t)P.face_line_off[i];
@@ -422,28 +397,6 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     }
     for (size_t l = 0; l < P.line_first.size(); ++l)
       linfo[l] = P.line_n[l] | (P.line_axis[l] << 16) | (P.line_kind[l] << 20);
-    // per cut cell: [line begin, volume/interface boundary, line end,
-    // (first line, end line, slot) of each cut face or (0, 0, -1)]
-    std::vector<int32_t> desc(P.cut.size() * 24, 0);
-    for (size_t i = 0; i < P.cut.size(); ++i) {
-      int32_t* d = &desc[i * 24];
-      const int32_t lb = (int32_t)P.cell_line_off[i], le = (int32_t)P.cell_line_off[i + 1];
-      int32_t mid = lb;
-      while (mid < le && P.line_kind[mid] == 0) ++mid;
-      d[0] = lb;
-      d[1] = mid;
-      d[2] = le;
-      for (int f = 0; f < 6; ++f) { d[3 + 3 * f] = 0; d[4 + 3 * f] = 0; d[5 + 3 * f] = -1; }
-      int nf = 0;
-      for (int sl = 0; sl < S; ++sl) {
-        int32_t fi = P.slot_face[(size_t)P.cut[i] * S + sl];
-        if (fi < 0 || P.faces[fi].kind != ufem::kFaceCut) continue;
-        d[3 + 3 * nf] = flb[fi];
-        d[4 + 3 * nf] = fle[fi];
-        d[5 + 3 * nf] = sl;
-        ++nf;
-      }
-    }
     // cut cells processed in decreasing order of quadrature work
     std::vector<int32_t> order(P.cut.size());
     std::iota(order.begin(), order.end(), 0);
@@ -598,15 +551,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       return fail(UFEM_EUNSUPPORTED, "ufem_setup: a cut cell has more lines or cut faces than one line batch holds");
     }
     int rc;
-    if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->cut_order, order)) ||
-        (rc = op->upload((void**)&op->cut_rank, P.cut)) || (rc = op->upload((void**)&op->nb, nb)) ||
-        (rc = op->upload((void**)&op->flags, flags)) || (rc = op->upload((void**)&op->slot_face, slot_face)) ||
-        (rc = op->upload((void**)&op->face_qoff, face_qoff)) || (rc = op->upload((void**)&op->face_qn, face_qn)) ||
-        (rc = op->upload((void**)&op->vol_off, P.vol_off)) || (rc = op->upload((void**)&op->surf_off, P.surf_off)) ||
-        (rc = op->upload((void**)&op->cell_line_off, cloff)) || (rc = op->upload((void**)&op->face_lbeg, flb)) ||
-        (rc = op->upload((void**)&op->face_lend, fle)) || (rc = op->upload((void**)&op->line_first, P.line_first)) ||
-        (rc = op->upload((void**)&op->line_info, linfo)) || (rc = op->upload((void**)&op->cell_desc, desc)) ||
-        (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
+    if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
         (rc = op->upload((void**)&op->kinfo_all, kall)) || (rc = op->upload((void**)&op->kface_inside, kfin)) ||
         (rc = op->upload((void**)&op->kface_cut, kfcu)) ||
         (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||

@@ -70,21 +70,6 @@ template <typename T>
 struct DevArgs {
   int32_t n_active, n_inside, n_cut;
   const int32_t* inside;     // active ranks of inside cells
-  const int32_t* cut_order;  // processing order: cut index per slot
-  const int32_t* cut_rank;   // active rank per cut index
-  const int32_t* nb;         // [n_active * 2D] neighbour rank or -1
-  const int32_t* flags;      // [n_active]
-  const int32_t* slot_face;  // [n_active * 2D] face index or -1
-  const int64_t* face_qoff;  // [n_faces] kappa offset of the SIPG points
-  const int32_t* face_qn;    // [n_faces]
-  const int32_t* cell_line_off;  // [n_cut + 1] point lines of each cut cell
-  const int32_t* face_lbeg;      // [n_faces] first point line of a cut face
-  const int32_t* face_lend;      // [n_faces]
-  const int32_t* line_first;     // first point of a line
-  const int32_t* line_info;      // count | axis << 16 | kind << 20
-  const int32_t* cell_desc;      // [n_cut * 24] line segments of each cut cell
-  // line batches (layout above): volume / interface lines of cut cells and
-  // cut-face lines; records and line descriptors
   // per position of the inside / cut list: (active rank, flags, neighbour
   // ranks of the 2d slots, -1 padding), 8 ints
   const int32_t* kinfo_inside;
@@ -93,6 +78,8 @@ struct DevArgs {
   // per position and slot: kappa offset of the structured face's points
   const int64_t* kface_inside;
   const int64_t* kface_cut;
+  // line batches (layout above): volume / interface lines of cut cells and
+  // cut-face lines; records and line descriptors
   const int32_t* vbrec;
   const int32_t* vdesc;
   const int32_t* fbrec;
@@ -104,8 +91,6 @@ struct DevArgs {
   const int32_t* sf_bp;
   const int32_t* sf_ax;
   int32_t n_sfaces;
-  const int64_t* vol_off;    // [n_cut + 1]
-  const int64_t* surf_off;   // [n_cut + 1]
   const T* vol_x;            // SoA: vol_x[a * n_vol + q]
   const T* vol_w;
   const T* surf_x;           // SoA
@@ -120,9 +105,9 @@ struct DevArgs {
   T hs;                      // h^(dim - 2)
   T tau, gamma;
   int32_t terms;             // term mask
-  int32_t parts;             // stage bits: 1 inside cells, 2 cut cells (whole cell on the
-                             // quadrature path, structured faces on the line path), 4 cut
-                             // volume and interface lines, 8 cut-face lines
+  int32_t parts;             // stage bits: 1 inside cells, 2 structured faces and ghost
+                             // penalty of the cut cells, 4 cut volume and interface
+                             // lines, 8 cut-face lines
 };
 
 // Launchers: the per-dimension operator kernels live in op_<prec>_<dim>d.hip,

@@ -1,23 +1,24 @@
 // HIP kernels of the matrix-free unfitted DG operator (gfx950).
 //
-// Cell-centric schedule: every active cell is owned by one workgroup, which
-// evaluates the cell integral and, for each of its 2d faces, the face flux
-// from both traces, and integrates only its own test functions.  Every DoF
-// is therefore written exactly once (v is overwritten, no atomics, no
-// colouring); each interior face flux is computed once from either side.
+// Cell-centric schedule: every row of v belongs to one cell and is written
+// by the wave that owns the cell in each stage, so no global atomics and no
+// colouring are needed; each interior face flux is computed from both sides.
 //
-//  * inside cells (structured quadrature, Section 3.2 "structured
-//    quadrature evaluation"): sum factorisation with the collocation
-//    derivative at the k^d Gauss points, and face-normal interpolation of the
-//    trace (value and normal derivative; the value is read directly thanks
-//    to the Gauss-Lobatto nodes) followed by in-face sum factorisation;
-//  * cut cells (Section 3.2 "unstructured quadrature evaluation"): the 1D
-//    Lagrange polynomials are evaluated at each point, value and gradient
-//    follow from d nested one-dimensional sums, and the transposed sums
-//    integrate; cut faces interpolate the face-normal trace structurally and
-//    then per point in the d-1 in-face directions.
-// The structured and unstructured contributions of a cell meet in the LDS
-// accumulator of the cell (the additive split y = y_str + y_unstr).
+//  * structured terms (Section 3.2, structured quadrature evaluation): with
+//    kappa = 1 the cell operator is a sum of Kronecker products of the 1D
+//    mass and stiffness matrices plus face terms at the Gauss-Lobatto face
+//    nodes (inside_kron_kernel, one lane per 1D line); with a kappa field
+//    the same line passes go through the k^d Gauss points, where the kappa
+//    of each point weights the integrand (kappa_struct_kernel);
+//  * cut cells (Section 3.2, unstructured quadrature evaluation): the points
+//    of the dimension-reduction quadrature lie on lines along one axis, so
+//    per line the d-1 off-axis 1D Lagrange factors are fixed and only the
+//    on-axis one changes from point to point (cut_batch_kernel for volume
+//    and interface lines, cut_face_kernel for the lines of the cut faces,
+//    whose face-normal traces are interpolated structurally first);
+//  * dL/dkappa (the adjoint pass): the same evaluations with both arguments,
+//    one value per quadrature point (inside_dk, face_dk, cut_dk,
+//    cut_face_dk kernels).
 #pragma once
 #include <algorithm>
 
@@ -32,15 +33,6 @@ constexpr __host__ __device__ int ipow(int b, int e) {
   return r;
 }
 
-template <int K, int D>
-struct Shape {
-  static constexpr int ND = ipow(K, D);
-  static constexpr int NF = ipow(K, D - 1);
-  static constexpr int NT = ND <= 64 ? 64 : (ND <= 128 ? 128 : 256);
-  static constexpr int PC = 64;          // points per chunk
-  static constexpr int PT = 6 * K + 4;   // per-point LDS record
-};
-
 __device__ __forceinline__ void sync() { __syncthreads(); }
 
 // Workgroups are handed to the 8 XCDs round robin, each XCD with its own L2.
@@ -53,20 +45,6 @@ __device__ __forceinline__ int xcd_block() {
   if (nb < kXcds) return b;
   const int q = nb / kXcds, r = nb % kXcds, x = b % kXcds, i = b / kXcds;
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
-// out = M (or M^T) applied along axis AX of a K^N tensor
-template <int K, int N, int AX, bool TR, bool ACC, typename T>
-__device__ __forceinline__ void contract(const T* __restrict__ M, const T* in, T* out) {
-  constexpr int NN = ipow(K, N), S = ipow(K, AX);
-  for (int idx = threadIdx.x; idx < NN; idx += blockDim.x) {
-    const int r = (idx / S) % K;
-    const int base = idx - r * S;
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < K; ++i) s += (TR ? M[i * K + r] : M[r * K + i]) * in[base + i * S];
-    out[idx] = ACC ? out[idx] + s : s;
-  }
 }
 
 // 1D GLL Lagrange values and first derivatives at t
@@ -87,90 +65,6 @@ __device__ __forceinline__ void lagrange1d(const T* __restrict__ X, const T* __r
   }
 }
 
-// value and reference gradient at a point from LDS DoFs (broadcast reads)
-template <int K, int D, typename T>
-__device__ __forceinline__ void eval_point(const T* u, const T* X, const T* dX, const T* Y, const T* dY, const T* Z,
-                                           const T* dZ, T& val, T* g) {
-  if constexpr (D == 3) {
-    T v = 0, gx = 0, gy = 0, gz = 0;
-#pragma unroll
-    for (int m = 0; m < K; ++m) {
-      // keep the loads of one z-layer together: only K^2 DoFs live at a time
-      __builtin_amdgcn_sched_barrier(0);
-      T c0 = 0, c1 = 0, c2 = 0;
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        T a = 0, b = 0;
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-          const T uu = u[i + K * j + K * K * m];
-          a += X[i] * uu;
-          b += dX[i] * uu;
-        }
-        c0 += Y[j] * a;
-        c1 += dY[j] * a;
-        c2 += Y[j] * b;
-      }
-      v += Z[m] * c0;
-      gz += dZ[m] * c0;
-      gy += Z[m] * c1;
-      gx += Z[m] * c2;
-    }
-    val = v;
-    g[0] = gx;
-    g[1] = gy;
-    g[2] = gz;
-  } else {
-    T v = 0, gx = 0, gy = 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      T a = 0, b = 0;
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        const T uu = u[i + K * j];
-        a += X[i] * uu;
-        b += dX[i] * uu;
-      }
-      v += Y[j] * a;
-      gy += dY[j] * a;
-      gx += Y[j] * b;
-    }
-    val = v;
-    g[0] = gx;
-    g[1] = gy;
-  }
-}
-
-// LDS workspace of one cell
-template <int K, int D, typename T, bool ADJ>
-struct Work {
-  static constexpr int ND = Shape<K, D>::ND, NF = Shape<K, D>::NF;
-  T tab[TabOff::size(K)];
-  T xo[ND], xn[ND];        // operand of the cell and of the current neighbour
-  T yo[ADJ ? ND : 1], yn[ADJ ? ND : 1];  // second argument of dkappa
-  T acc[ND];
-  T t[5][ND];
-  T f[6][NF];
-  T pts[ADJ ? Shape<K, D>::PC * Shape<K, D>::PT : 1];  // point records (adjoint pass)
-  T nbuf[ADJ ? 1 : 2 * D][ADJ ? 1 : ND];              // all neighbours (apply)
-};
-
-// the apply's neighbours of a cell, all loaded at once (slots with a
-// structured SIPG or ghost-penalty term)
-template <int K, int D, typename T, bool ADJ>
-__device__ __forceinline__ void load_neighbours(Work<K, D, T, ADJ>& W, const T* __restrict__ x, const int* nbr,
-                                                int fl, int terms) {
-  constexpr int ND = Shape<K, D>::ND;
-  if constexpr (!ADJ) {
-#pragma unroll
-    for (int s = 0; s < 2 * D; ++s) {
-      const bool on = ((terms & 2) && ((fl >> (kFlagStr + s)) & 1)) || ((terms & 8) && ((fl >> (kFlagGP + s)) & 1));
-      if (!on) continue;
-      for (int l = threadIdx.x; l < ND; l += blockDim.x) W.nbuf[s][l] = x[(int64_t)nbr[s] * ND + l];
-    }
-  }
-}
-
 // cell index of in-face node f at layer l along `axis`
 template <int K, int D>
 __device__ __forceinline__ int cell_index(int axis, int f, int l) {
@@ -183,536 +77,6 @@ __device__ __forceinline__ int cell_index(int axis, int f, int l) {
     return f0 + K * f1 + K * K * l;
   }
 }
-
-template <int K, int N, typename T>
-__device__ __forceinline__ T tensor_weight(const T* W, int q) {
-  T w = 1;
-#pragma unroll
-  for (int a = 0; a < N; ++a) {
-    w *= W[q % K];
-    q /= K;
-  }
-  return w;
-}
-
-// gradient at the Gauss points of a structured cell: G[a] = d_a u
-template <int K, int D, typename T>
-__device__ void grad_gauss(const T* tab, const T* u, T* A, T* B, T* G0, T* G1, T* G2) {
-  const T* S = tab + TabOff::S(K);
-  const T* DG = tab + TabOff::DG(K);
-  if constexpr (D == 3) {
-    contract<K, 3, 0, false, false>(S, u, A);
-    sync();
-    contract<K, 3, 1, false, false>(S, A, B);
-    sync();
-    contract<K, 3, 2, false, false>(S, B, A);
-    sync();
-    contract<K, 3, 0, false, false>(DG, A, G0);
-    contract<K, 3, 1, false, false>(DG, A, G1);
-    contract<K, 3, 2, false, false>(DG, A, G2);
-    sync();
-  } else {
-    contract<K, 2, 0, false, false>(S, u, A);
-    sync();
-    contract<K, 2, 1, false, false>(S, A, B);
-    sync();
-    contract<K, 2, 0, false, false>(DG, B, G0);
-    contract<K, 2, 1, false, false>(DG, B, G1);
-    sync();
-  }
-}
-
-// acc += integration of the reference-gradient coefficients G at the Gauss points
-template <int K, int D, typename T>
-__device__ void int_gauss(const T* tab, T* G0, T* G1, T* G2, T* A, T* B, T* acc) {
-  const T* S = tab + TabOff::S(K);
-  const T* DG = tab + TabOff::DG(K);
-  if constexpr (D == 3) {
-    contract<K, 3, 0, true, false>(DG, G0, A);
-    sync();
-    contract<K, 3, 1, true, true>(DG, G1, A);
-    sync();
-    contract<K, 3, 2, true, true>(DG, G2, A);
-    sync();
-    contract<K, 3, 2, true, false>(S, A, B);
-    sync();
-    contract<K, 3, 1, true, false>(S, B, A);
-    sync();
-    contract<K, 3, 0, true, true>(S, A, acc);
-    sync();
-  } else {
-    contract<K, 2, 0, true, false>(DG, G0, A);
-    sync();
-    contract<K, 2, 1, true, true>(DG, G1, A);
-    sync();
-    contract<K, 2, 1, true, false>(S, A, B);
-    sync();
-    contract<K, 2, 0, true, true>(S, B, acc);
-    sync();
-  }
-}
-
-// volume term of an inside cell
-template <int K, int D, typename T, bool ADJ>
-__device__ void volume_structured(Work<K, D, T, ADJ>& W, const DevArgs<T>& a, int64_t koff, T* dkappa) {
-  constexpr int ND = Shape<K, D>::ND;
-  T* G2 = D == 3 ? W.t[4] : W.t[3];
-  grad_gauss<K, D>(W.tab, W.xo, W.t[0], W.t[1], W.t[2], W.t[3], G2);
-  const T* Wt = W.tab + TabOff::W(K);
-  if constexpr (ADJ) {
-    // gradient of the second argument into t[0], t[1], (xn as third)
-    if (dkappa) {
-      grad_gauss<K, D>(W.tab, W.yo, W.acc, W.xn, W.t[0], W.t[1], W.yn);
-      for (int q = threadIdx.x; q < ND; q += blockDim.x) {
-        T s = W.t[0][q] * W.t[2][q] + W.t[1][q] * W.t[3][q];
-        if constexpr (D == 3) s += W.yn[q] * G2[q];
-        dkappa[koff + q] = a.hs * tensor_weight<K, D>(Wt, q) * s;
-      }
-      sync();
-      for (int q = threadIdx.x; q < ND; q += blockDim.x) W.acc[q] = 0;
-      sync();
-    }
-  }
-  for (int q = threadIdx.x; q < ND; q += blockDim.x) {
-    T c = a.hs * tensor_weight<K, D>(Wt, q);
-    if (a.kappa) c *= a.kappa[koff + q];
-    W.t[2][q] *= c;
-    W.t[3][q] *= c;
-    if constexpr (D == 3) G2[q] *= c;
-  }
-  sync();
-  int_gauss<K, D>(W.tab, W.t[2], W.t[3], G2, W.t[0], W.t[1], W.acc);
-}
-
-// traces of own (o) and neighbour (n) cell: jump = sigma (o - n) of the
-// order-j normal derivative, and the average of the first derivative
-template <int K, int D, typename T>
-__device__ __forceinline__ T trace(const T* E, const T* u, int axis, int f) {
-  T s = 0;
-#pragma unroll
-  for (int l = 0; l < K; ++l) s += E[l] * u[cell_index<K, D>(axis, f, l)];
-  return s;
-}
-
-// in-face Gauss interpolation / its transpose on a K^(D-1) face field
-template <int K, int D, bool TR, typename T>
-__device__ void face_interp(const T* S, T* fld, T* tmp) {
-  if constexpr (D == 3) {
-    if (!TR) {
-      contract<K, 2, 0, false, false>(S, fld, tmp);
-      sync();
-      contract<K, 2, 1, false, false>(S, tmp, fld);
-      sync();
-    } else {
-      contract<K, 2, 1, true, false>(S, fld, tmp);
-      sync();
-      contract<K, 2, 0, true, false>(S, tmp, fld);
-      sync();
-    }
-  } else {
-    contract<K, 1, 0, TR, false>(S, fld, tmp);
-    sync();
-    for (int i = threadIdx.x; i < K; i += blockDim.x) fld[i] = tmp[i];
-    sync();
-  }
-}
-
-// structured SIPG flux (full-face Gauss rule) of slot (axis, side)
-template <int K, int D, typename T, bool ADJ>
-__device__ void face_sipg_structured(Work<K, D, T, ADJ>& W, const DevArgs<T>& a, int axis, int side, int64_t koff,
-                                     T* dkappa) {
-  constexpr int NF = Shape<K, D>::NF, ND = Shape<K, D>::ND;
-  const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-  const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-  const T sigma = side ? T(1) : T(-1);
-  const T* S = W.tab + TabOff::S(K);
-  const T* Wt = W.tab + TabOff::W(K);
-  for (int f = threadIdx.x; f < NF; f += blockDim.x) {
-    W.f[0][f] = sigma * (trace<K, D>(Eo, W.xo, axis, f) - trace<K, D>(En, W.xn, axis, f));
-    W.f[1][f] = T(0.5) * (trace<K, D>(Eo + K, W.xo, axis, f) + trace<K, D>(En + K, W.xn, axis, f));
-    if constexpr (ADJ) {
-      W.f[3][f] = sigma * (trace<K, D>(Eo, W.yo, axis, f) - trace<K, D>(En, W.yn, axis, f));
-      W.f[4][f] = T(0.5) * (trace<K, D>(Eo + K, W.yo, axis, f) + trace<K, D>(En + K, W.yn, axis, f));
-    }
-  }
-  sync();
-  face_interp<K, D, false>(S, W.f[0], W.f[2]);
-  face_interp<K, D, false>(S, W.f[1], W.f[2]);
-  if constexpr (ADJ) {
-    face_interp<K, D, false>(S, W.f[3], W.f[2]);
-    face_interp<K, D, false>(S, W.f[4], W.f[2]);
-  }
-  for (int f = threadIdx.x; f < NF; f += blockDim.x) {
-    const T w = a.hs * tensor_weight<K, D - 1>(Wt, f);
-    const T j = W.f[0][f], av = W.f[1][f];
-    if constexpr (ADJ) {
-      if (dkappa && side == 1) {
-        const T ju = W.f[3][f], au = W.f[4][f];
-        dkappa[koff + f] = w * (-av * ju - j * au + a.gamma * j * ju);
-      }
-    }
-    const T c = a.kappa ? w * a.kappa[koff + f] : w;
-    W.f[0][f] = c * sigma * (a.gamma * j - av);
-    W.f[1][f] = T(-0.5) * c * j;
-  }
-  sync();
-  face_interp<K, D, true>(S, W.f[0], W.f[2]);
-  face_interp<K, D, true>(S, W.f[1], W.f[2]);
-  for (int idx = threadIdx.x; idx < ND; idx += blockDim.x) {
-    int f, l;
-    if constexpr (D == 2) {
-      l = axis == 0 ? idx % K : idx / K;
-      f = axis == 0 ? idx / K : idx % K;
-    } else {
-      const int i = idx % K, jj = (idx / K) % K, m = idx / (K * K);
-      if (axis == 0) { l = i; f = jj + K * m; }
-      else if (axis == 1) { l = jj; f = i + K * m; }
-      else { l = m; f = i + K * jj; }
-    }
-    W.acc[idx] += Eo[l] * W.f[0][f] + Eo[K + l] * W.f[1][f];
-  }
-  sync();
-}
-
-// face ghost penalty of slot (axis, side), orders j with gamma_j != 0
-template <int K, int D, typename T, bool ADJ>
-__device__ void face_ghost(Work<K, D, T, ADJ>& W, const DevArgs<T>& a, int axis, int side) {
-  constexpr int NF = Shape<K, D>::NF, ND = Shape<K, D>::ND;
-  const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-  const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-  const T sigma = side ? T(1) : T(-1);
-  const T* S = W.tab + TabOff::S(K);
-  const T* Wt = W.tab + TabOff::W(K);
-  const T* GW = W.tab + TabOff::GW(K);
-  for (int j = 0; j < K; ++j) {
-    const T gj = GW[j];
-    if (gj == T(0)) continue;
-    for (int f = threadIdx.x; f < NF; f += blockDim.x)
-      W.f[0][f] = sigma * (trace<K, D>(Eo + j * K, W.xo, axis, f) - trace<K, D>(En + j * K, W.xn, axis, f));
-    sync();
-    face_interp<K, D, false>(S, W.f[0], W.f[2]);
-    for (int f = threadIdx.x; f < NF; f += blockDim.x) W.f[0][f] *= a.hs * gj * tensor_weight<K, D - 1>(Wt, f);
-    sync();
-    face_interp<K, D, true>(S, W.f[0], W.f[2]);
-    for (int idx = threadIdx.x; idx < ND; idx += blockDim.x) {
-      int f, l;
-      if constexpr (D == 2) {
-        l = axis == 0 ? idx % K : idx / K;
-        f = axis == 0 ? idx / K : idx % K;
-      } else {
-        const int i = idx % K, jj = (idx / K) % K, m = idx / (K * K);
-        if (axis == 0) { l = i; f = jj + K * m; }
-        else if (axis == 1) { l = jj; f = i + K * m; }
-        else { l = m; f = i + K * jj; }
-      }
-      W.acc[idx] += sigma * Eo[j * K + l] * W.f[0][f];
-    }
-    sync();
-  }
-}
-
-// SIPG flux on a cut face: structured face-normal trace, per-point in-face
-// interpolation (d-1 dimensions), per-point flux, transposed in-face sums
-template <int K, int D, typename T, bool ADJ>
-__device__ void face_sipg_cut(Work<K, D, T, ADJ>& W, const DevArgs<T>& a, int axis, int side, int64_t koff, int nq,
-                              T* dkappa) {
-  constexpr int NF = Shape<K, D>::NF, ND = Shape<K, D>::ND, PC = Shape<K, D>::PC;
-  constexpr int RS = 2 * K + 4;  // per-point record: in-face basis (2K), cv, cd, (ADJ: unused)
-  const T* Eo = W.tab + (side ? TabOff::E1(K) : TabOff::E0(K));
-  const T* En = W.tab + (side ? TabOff::E0(K) : TabOff::E1(K));
-  const T sigma = side ? T(1) : T(-1);
-  const T* Xn = W.tab + TabOff::X(K);
-  const T* ID = W.tab + TabOff::ID(K);
-  for (int f = threadIdx.x; f < NF; f += blockDim.x) {
-    W.f[0][f] = sigma * (trace<K, D>(Eo, W.xo, axis, f) - trace<K, D>(En, W.xn, axis, f));
-    W.f[1][f] = T(0.5) * (trace<K, D>(Eo + K, W.xo, axis, f) + trace<K, D>(En + K, W.xn, axis, f));
-    if constexpr (ADJ) {
-      W.f[3][f] = sigma * (trace<K, D>(Eo, W.yo, axis, f) - trace<K, D>(En, W.yn, axis, f));
-      W.f[4][f] = T(0.5) * (trace<K, D>(Eo + K, W.yo, axis, f) + trace<K, D>(En + K, W.yn, axis, f));
-    }
-    W.f[2][f] = 0;  // CV accumulator
-    W.f[5][f] = 0;  // CD accumulator
-  }
-  sync();
-  const int64_t base = koff - a.seg[3];
-  for (int c0 = 0; c0 < nq; c0 += PC) {
-    const int npt = min(PC, nq - c0);
-    for (int qi = threadIdx.x; qi < npt; qi += blockDim.x) {
-      const int64_t q = base + c0 + qi;
-      T* rec = W.pts + qi * RS;
-      T Y[K], dY[K], Z[K], dZ[K];
-      lagrange1d<K>(Xn, ID, a.fcut_x[q], Y, dY);
-      if constexpr (D == 3) lagrange1d<K>(Xn, ID, a.fcut_x[a.n_fcut + q], Z, dZ);
-      T j = 0, av = 0, ju = 0, au = 0;
-      if constexpr (D == 3) {
-#pragma unroll
-        for (int m = 0; m < K; ++m) {
-          T sj = 0, sa = 0, sju = 0, sau = 0;
-#pragma unroll
-          for (int i = 0; i < K; ++i) {
-            sj += Y[i] * W.f[0][i + K * m];
-            sa += Y[i] * W.f[1][i + K * m];
-            if constexpr (ADJ) {
-              sju += Y[i] * W.f[3][i + K * m];
-              sau += Y[i] * W.f[4][i + K * m];
-            }
-          }
-          j += Z[m] * sj;
-          av += Z[m] * sa;
-          ju += Z[m] * sju;
-          au += Z[m] * sau;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-          j += Y[i] * W.f[0][i];
-          av += Y[i] * W.f[1][i];
-          if constexpr (ADJ) {
-            ju += Y[i] * W.f[3][i];
-            au += Y[i] * W.f[4][i];
-          }
-        }
-      }
-      const T w = a.hs * a.fcut_w[q];
-      if constexpr (ADJ) {
-        if (dkappa && side == 1) dkappa[koff + c0 + qi] = w * (-av * ju - j * au + a.gamma * j * ju);
-      }
-      const T c = a.kappa ? w * a.kappa[koff + c0 + qi] : w;
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        rec[i] = Y[i];
-        if constexpr (D == 3) rec[K + i] = Z[i];
-      }
-      rec[2 * K] = c * sigma * (a.gamma * j - av);
-      rec[2 * K + 1] = T(-0.5) * c * j;
-    }
-    sync();
-    for (int f = threadIdx.x; f < NF; f += blockDim.x) {
-      const int fi = f % K, fm = f / K;
-      T cv = 0, cd = 0;
-      for (int qi = 0; qi < npt; ++qi) {
-        const T* rec = W.pts + qi * RS;
-        const T bf = D == 3 ? rec[fi] * rec[K + fm] : rec[fi];
-        cv += bf * rec[2 * K];
-        cd += bf * rec[2 * K + 1];
-      }
-      W.f[2][f] += cv;
-      W.f[5][f] += cd;
-    }
-    sync();
-  }
-  for (int idx = threadIdx.x; idx < ND; idx += blockDim.x) {
-    int f, l;
-    if constexpr (D == 2) {
-      l = axis == 0 ? idx % K : idx / K;
-      f = axis == 0 ? idx / K : idx % K;
-    } else {
-      const int i = idx % K, jj = (idx / K) % K, m = idx / (K * K);
-      if (axis == 0) { l = i; f = jj + K * m; }
-      else if (axis == 1) { l = jj; f = i + K * m; }
-      else { l = m; f = i + K * jj; }
-    }
-    W.acc[idx] += Eo[l] * W.f[2][f] + Eo[K + l] * W.f[5][f];
-  }
-  sync();
-}
-
-// volume (SURF = false) or interface (SURF = true) points of a cut cell
-template <int K, int D, bool SURF, typename T, bool ADJ>
-__device__ void cut_points(Work<K, D, T, ADJ>& W, const DevArgs<T>& a, int64_t q0, int nq, int64_t koff, T* dkappa) {
-  constexpr int ND = Shape<K, D>::ND, PC = Shape<K, D>::PC, PT = Shape<K, D>::PT;
-  const T* Xn = W.tab + TabOff::X(K);
-  const T* ID = W.tab + TabOff::ID(K);
-  const int64_t npts = SURF ? a.n_surf : a.n_vol;
-  const T* px = SURF ? a.surf_x : a.vol_x;
-  const T* pw = SURF ? a.surf_w : a.vol_w;
-  for (int c0 = 0; c0 < nq; c0 += PC) {
-    const int npt = min(PC, nq - c0);
-    for (int qi = threadIdx.x; qi < npt; qi += blockDim.x) {
-      const int64_t q = q0 + c0 + qi;
-      T* rec = W.pts + qi * PT;
-      T* B = rec;  // X, dX, Y, dY, Z, dZ
-      lagrange1d<K>(Xn, ID, px[q], B, B + K);
-      lagrange1d<K>(Xn, ID, px[npts + q], B + 2 * K, B + 3 * K);
-      if constexpr (D == 3) lagrange1d<K>(Xn, ID, px[2 * npts + q], B + 4 * K, B + 5 * K);
-      T val, g[3] = {0, 0, 0};
-      eval_point<K, D>(W.xo, B, B + K, B + 2 * K, B + 3 * K, B + 4 * K, B + 5 * K, val, g);
-      const T w = a.hs * pw[q];
-      T n[3] = {0, 0, 0};
-      if constexpr (SURF) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) n[d] = a.surf_n[d * npts + q];
-      }
-      if constexpr (ADJ) {
-        if (dkappa) {
-          T val2, g2[3] = {0, 0, 0};
-          eval_point<K, D>(W.yo, B, B + K, B + 2 * K, B + 3 * K, B + 4 * K, B + 5 * K, val2, g2);
-          T s;
-          if constexpr (SURF) {
-            T dn = 0, dn2 = 0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-              dn += n[d] * g[d];
-              dn2 += n[d] * g2[d];
-            }
-            s = -dn * val2 - val * dn2 + a.tau * val * val2;
-          } else {
-            s = 0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) s += g[d] * g2[d];
-          }
-          dkappa[koff + c0 + qi] = w * s;
-        }
-      }
-      const T c = a.kappa ? w * a.kappa[koff + c0 + qi] : w;
-      T* F = rec + 6 * K;
-      if constexpr (SURF) {
-        T dn = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) dn += n[d] * g[d];
-        F[0] = c * (a.tau * val - dn);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) F[1 + d] = -c * val * n[d];
-      } else {
-        F[0] = 0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) F[1 + d] = c * g[d];
-      }
-    }
-    sync();
-    for (int l = threadIdx.x; l < ND; l += blockDim.x) {
-      const int i = l % K, jj = (l / K) % K, m = D == 3 ? l / (K * K) : 0;
-      T s = 0;
-      for (int qi = 0; qi < npt; ++qi) {
-        const T* rec = W.pts + qi * PT;
-        const T* F = rec + 6 * K;
-        const T xi = rec[i], dxi = rec[K + i], yj = rec[2 * K + jj], dyj = rec[3 * K + jj];
-        if constexpr (D == 3) {
-          const T zm = rec[4 * K + m], dzm = rec[5 * K + m];
-          s += xi * yj * (zm * F[0] + dzm * F[3]) + zm * (dxi * yj * F[1] + xi * dyj * F[2]);
-        } else {
-          s += xi * yj * F[0] + dxi * yj * F[1] + xi * dyj * F[2];
-        }
-      }
-      W.acc[l] += s;
-    }
-    sync();
-  }
-}
-
-template <int K, int D, typename T, bool ADJ>
-__device__ void load_tab(Work<K, D, T, ADJ>& W, const T* tab) {
-  for (int i = threadIdx.x; i < TabOff::size(K); i += blockDim.x) W.tab[i] = tab[i];
-}
-
-template <int K, int D, typename T, bool ADJ>
-__device__ void load_cell(T* dst, const T* src, int r) {
-  constexpr int ND = Shape<K, D>::ND;
-  const T* s = src + (int64_t)r * ND;
-  for (int l = threadIdx.x; l < ND; l += blockDim.x) dst[l] = s[l];
-}
-
-// ---------------------------------------------------------------- kernels
-template <int K, int D, typename T, bool ADJ>
-__global__ void __launch_bounds__((Shape<K, D>::NT)) inside_kernel(DevArgs<T> a, const T* __restrict__ x,
-                                                                 const T* __restrict__ y, T* __restrict__ v,
-                                                                 T* __restrict__ dkappa) {
-  constexpr int ND = Shape<K, D>::ND;
-  __shared__ Work<K, D, T, ADJ> W;
-  load_tab<K, D>(W, a.tab);
-  for (int ci = blockIdx.x; ci < a.n_inside; ci += gridDim.x) {
-    // rank, flags and neighbours in one load (uniform across the block)
-    const int4 k0 = reinterpret_cast<const int4*>(a.kinfo_inside)[2 * ci];
-    const int4 k1 = reinterpret_cast<const int4*>(a.kinfo_inside)[2 * ci + 1];
-    const int r = k0.x, fl = k0.y;
-    const int nbrs[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
-    load_cell<K, D, T, ADJ>(W.xo, x, r);
-    if constexpr (ADJ) load_cell<K, D, T, ADJ>(W.yo, y, r);
-    load_neighbours<K, D>(W, x, nbrs, fl, a.terms);
-    for (int l = threadIdx.x; l < ND; l += blockDim.x) W.acc[l] = 0;
-    sync();
-    if (a.terms & 1) volume_structured<K, D>(W, a, a.seg[0] + (int64_t)ci * ND, dkappa);
-    for (int s = 0; s < 2 * D; ++s) {
-      const bool sipg = (a.terms & 2) && ((fl >> (kFlagStr + s)) & 1);
-      const bool gp = (a.terms & 8) && ((fl >> (kFlagGP + s)) & 1);
-      if (!sipg && !gp) continue;
-      const int nbr = nbrs[s];
-      if constexpr (ADJ) {
-        load_cell<K, D, T, ADJ>(W.xn, x, nbr);
-        load_cell<K, D, T, ADJ>(W.yn, y, nbr);
-      } else {
-        for (int l = threadIdx.x; l < ND; l += blockDim.x) W.xn[l] = W.nbuf[s][l];
-      }
-      sync();
-      if (sipg) {
-        const int fid = a.slot_face[(int64_t)r * 2 * D + s];
-        face_sipg_structured<K, D>(W, a, s >> 1, s & 1, a.face_qoff[fid], dkappa);
-      }
-      if (gp) face_ghost<K, D>(W, a, s >> 1, s & 1);
-    }
-    T* out = v + (int64_t)r * ND;
-    for (int l = threadIdx.x; l < ND; l += blockDim.x) out[l] = W.acc[l];
-    sync();
-  }
-}
-
-template <int K, int D, typename T, bool ADJ>
-__global__ void __launch_bounds__((Shape<K, D>::NT)) cut_kernel(DevArgs<T> a, const T* __restrict__ x,
-                                                              const T* __restrict__ y, T* __restrict__ v,
-                                                              T* __restrict__ dkappa) {
-  constexpr int ND = Shape<K, D>::ND;
-  __shared__ Work<K, D, T, ADJ> W;
-  load_tab<K, D>(W, a.tab);
-  for (int slot = blockIdx.x; slot < a.n_cut; slot += gridDim.x) {
-    const int ci = a.cut_order[slot];
-    const int4 k0 = reinterpret_cast<const int4*>(a.kinfo_cut)[2 * ci];
-    const int4 k1 = reinterpret_cast<const int4*>(a.kinfo_cut)[2 * ci + 1];
-    const int r = k0.x, fl = k0.y;
-    const int nbrs[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
-    load_cell<K, D, T, ADJ>(W.xo, x, r);
-    if constexpr (ADJ) load_cell<K, D, T, ADJ>(W.yo, y, r);
-    load_neighbours<K, D>(W, x, nbrs, fl, a.terms);
-    for (int l = threadIdx.x; l < ND; l += blockDim.x) W.acc[l] = 0;
-    sync();
-    // the apply leaves the volume, interface and cut-face points to the line
-    // kernels (structured faces and ghost penalty only); the adjoint pass
-    // evaluates every term here
-    if constexpr (ADJ) {
-      if (a.terms & 1) {
-        const int64_t q0 = a.vol_off[ci];
-        cut_points<K, D, false>(W, a, q0, (int)(a.vol_off[ci + 1] - q0), a.seg[1] + q0, dkappa);
-      }
-      if (a.terms & 4) {
-        const int64_t q0 = a.surf_off[ci];
-        cut_points<K, D, true>(W, a, q0, (int)(a.surf_off[ci + 1] - q0), a.seg[4] + q0, dkappa);
-      }
-    }
-    for (int s = 0; s < 2 * D; ++s) {
-      const bool str = (a.terms & 2) && ((fl >> (kFlagStr + s)) & 1);
-      const bool cutf = ADJ && (a.terms & 2) && ((fl >> (kFlagCut + s)) & 1);
-      const bool gp = (a.terms & 8) && ((fl >> (kFlagGP + s)) & 1);
-      if (!str && !cutf && !gp) continue;
-      const int nbr = nbrs[s];
-      if constexpr (ADJ) {
-        load_cell<K, D, T, ADJ>(W.xn, x, nbr);
-        load_cell<K, D, T, ADJ>(W.yn, y, nbr);
-      } else {
-        for (int l = threadIdx.x; l < ND; l += blockDim.x) W.xn[l] = W.nbuf[s][l];
-      }
-      sync();
-      const int fid = a.slot_face[(int64_t)r * 2 * D + s];
-      if (str) face_sipg_structured<K, D>(W, a, s >> 1, s & 1, a.face_qoff[fid], dkappa);
-      if constexpr (ADJ) {
-        if (cutf) face_sipg_cut<K, D>(W, a, s >> 1, s & 1, a.face_qoff[fid], a.face_qn[fid], dkappa);
-      }
-      if (gp) face_ghost<K, D>(W, a, s >> 1, s & 1);
-    }
-    T* out = v + (int64_t)r * ND;
-    for (int l = threadIdx.x; l < ND; l += blockDim.x) out[l] = W.acc[l];
-    sync();
-  }
-}
-
 
 // ------------------------------------------------ inside cells, kappa = 1
 // With a constant coefficient, exact Gauss integration and the Cartesian
@@ -2580,17 +1944,14 @@ int blocks_per_cu(Kern kernel) {
 
 template <int K, int D, typename T>
 hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, bool adj, hipStream_t s) {
-  constexpr int NT = Shape<K, D>::NT;
-  const int gi = (a.parts & 1) ? (int)std::min<int64_t>(a.n_inside, 1 << 20) : 0;
-  const int gc = (a.parts & 2) ? (int)std::min<int64_t>(a.n_cut, 1 << 20) : 0;
-  if (adj && ipow(K, D) <= 125) {
-    // A is symmetric: A^T w is the fast apply of w; dkappa from the
-    // evaluation kernels
+  if (adj) {
+    // A is symmetric: A^T w is the apply of w; dkappa from the evaluation
+    // kernels
     DevArgs<T> b = a;
     b.parts = 15;
     hipError_t e = launch_kd<K, D, T>(b, x, nullptr, v, nullptr, false, s);
     if (e != hipSuccess || dk == nullptr) return e;
-    if constexpr (ipow(K, D) <= 125) {
+    {
       constexpr int CW = KronShape<K, D>::C, CF = FaceDkShape<K, D>::C;
       if (a.n_inside > 0)
         inside_dk_kernel<K, D, T><<<(int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20), 64, 0, s>>>(a, x, y, dk);
@@ -2605,56 +1966,49 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     }
     return hipGetLastError();
   }
-  if (!adj) {
-    const bool both = a.kappa == nullptr && (a.parts & 3) == 3;
-    if (both) {
-      // inside cells and the structured faces of the cut cells in one launch
-      constexpr int CW = KronShape<K, D>::C;
-      const int64_t n_all = a.n_inside + a.n_cut;
-      const int gk = (int)std::min<int64_t>((n_all + CW - 1) / CW, 1 << 20);
-      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_all, (int)n_all, 1);
-    } else if (a.kappa == nullptr) {
-      constexpr int CW = KronShape<K, D>::C;
-      const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
-      if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
-    } else {
-      constexpr int CW = KronShape<K, D>::C;
-      const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
-      if (gk > 0)
-        kappa_struct_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.kface_inside,
-                                                                        a.n_inside, 1);
-    }
-    {
-      // structured faces and ghost penalty of the cut cells (overwrites
-      // their rows: Kronecker kernel with kappa = 1, per-point face
-      // quadrature with kappa), then the volume / interface lines and the
-      // cut-face lines are added
-      constexpr int CW = KronShape<K, D>::C;
-      const int gs = (a.parts & 2) && !both ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
-      if (gs > 0) {
-        if (a.kappa == nullptr)
-          inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
-        else
-          kappa_struct_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.kface_cut, a.n_cut,
-                                                                          0);
-      }
-      if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
-        static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
-        const int g = std::min(a.n_vbatch, nb * a.n_cu);
-        cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);
-      }
-      if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0) {
-        static const int nb = blocks_per_cu(cut_face_kernel<K, D, T>);
-        const int g = std::min(a.n_fbatch, nb * a.n_cu);
-        cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
-      }
-    }
-    return hipGetLastError();
+  const bool both = a.kappa == nullptr && (a.parts & 3) == 3;
+  if (both) {
+    // inside cells and the structured faces of the cut cells in one launch
+    constexpr int CW = KronShape<K, D>::C;
+    const int64_t n_all = a.n_inside + a.n_cut;
+    const int gk = (int)std::min<int64_t>((n_all + CW - 1) / CW, 1 << 20);
+    if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_all, (int)n_all, 1);
+  } else if (a.kappa == nullptr) {
+    constexpr int CW = KronShape<K, D>::C;
+    const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
+    if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
+  } else {
+    constexpr int CW = KronShape<K, D>::C;
+    const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
+    if (gk > 0)
+      kappa_struct_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.kface_inside,
+                                                                      a.n_inside, 1);
   }
-  // adjoint pass with K^d > 125: A^T w and dkappa by the quadrature-path
-  // kernels
-  if (gi > 0) inside_kernel<K, D, T, true><<<gi, NT, 0, s>>>(a, x, y, v, dk);
-  if (gc > 0) cut_kernel<K, D, T, true><<<gc, NT, 0, s>>>(a, x, y, v, dk);
+  {
+    // structured faces and ghost penalty of the cut cells (overwrites
+    // their rows: Kronecker kernel with kappa = 1, per-point face
+    // quadrature with kappa), then the volume / interface lines and the
+    // cut-face lines are added
+    constexpr int CW = KronShape<K, D>::C;
+    const int gs = (a.parts & 2) && !both ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
+    if (gs > 0) {
+      if (a.kappa == nullptr)
+        inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
+      else
+        kappa_struct_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.kface_cut, a.n_cut,
+                                                                        0);
+    }
+    if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
+      static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
+      const int g = std::min(a.n_vbatch, nb * a.n_cu);
+      cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);
+    }
+    if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0) {
+      static const int nb = blocks_per_cu(cut_face_kernel<K, D, T>);
+      const int g = std::min(a.n_fbatch, nb * a.n_cu);
+      cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
+    }
+  }
   return hipGetLastError();
 }
 

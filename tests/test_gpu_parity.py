@@ -78,7 +78,8 @@ def test_apply_fp32(torch, name):
     assert _rel(v, ref) < TOL32
 
 
-@pytest.mark.parametrize("name", ["disk2d_p2", "ball3d_p2", "ball3d_p3", "balls3d_p2"])
+@pytest.mark.parametrize("name", ["disk2d_p2", "disk2d_p7", "ball3d_p2", "ball3d_p3", "ball3d_p5", "ball3d_p7",
+                                  "balls3d_p2"])
 def test_adjoint_and_dkappa_with_variable_kappa(torch, name):
     wl, ora, pl, op, u, w = _setup(name)
     _say(f"[{name}] adjoint")
@@ -116,8 +117,8 @@ def test_adjoint_and_dkappa_constant_kappa(torch, name):
 @pytest.mark.parametrize("name", ["ball3d_p3", "disk2d_p2", "balls3d_p2"])
 def test_apply_stages_compose(torch, name):
     """The kernel stages, one call each, give ufem_apply bit for bit, on the
-    kappa = 1 path (structured faces, then volume/interface and cut-face
-    lines) and on the quadrature path of a kappa field."""
+    kappa = 1 path (Kronecker kernel, then volume/interface and cut-face
+    lines) and with a kappa field (structured terms per Gauss point)."""
     from paper_2404_07911_amd import PART_CUT, PART_INSIDE, UfemError
 
     wl, ora, pl, op, u, w = _setup(name)
