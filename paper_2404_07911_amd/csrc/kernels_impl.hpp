@@ -1018,18 +1018,37 @@ __device__ __forceinline__ int2 batch_desc(const int32_t* __restrict__ desc, int
 
 // ---- volume and interface lines
 // Every entry of a volume batch is one cut cell.  In 3D the records of a
-// round are reduced by groups of K^2 lanes, lane (i1, ik) of a group forming
-// P = V1[i1] D0[ik] + dV1[i1] D1[ik] and Q = V1[i1] D2[ik] for one record and
-// adding V2[i2] P + dV2[i2] Q to its K DoFs (ik, i1, i2), i2 = 0..K-1; the
-// 64 / K^2 groups take every G-th record and are added into the cell's LDS
-// row with LDS atomics.  (2D: one lane per DoF.)
+// round are reduced by groups of lanes: lane (ik, tile) of a group owns the
+// DoFs (ik, i1, i2) with i1 in its tile of the i1 range and all i2; per
+// record it forms P = V1[i1] D0[ik] + dV1[i1] D1[ik] and Q = V1[i1] D2[ik]
+// for its i1 and adds V2[i2] P + dV2[i2] Q to its DoFs.  The G groups take
+// every G-th record and are added into the cell's LDS row with LDS atomics;
+// group g visits its i1 and i2 in an order rotated by g, so that the groups'
+// atomic adds of one instruction go to distinct addresses.  The rows are kept
+// in double for both precisions: LDS atomic adds of doubles are native and
+// cheap on gfx950, those of floats cost several times more (measured), and
+// the float operator's lines stay in float up to that last sum.  (2D: one
+// lane per DoF.)
+template <int K>
+struct ReduceShape {
+  // i1 tile: at most 32 / K rows, so that a lane holds at most 32 sums
+#ifndef UFEM_RB
+#define UFEM_RB 32
+#endif
+  static constexpr int AMAX = K < UFEM_RB / K ? K : (UFEM_RB / K > 0 ? UFEM_RB / K : 1);
+  static constexpr int NTL = (K + AMAX - 1) / AMAX;  // tiles
+  static constexpr int A = (K + NTL - 1) / NTL;      // rows per tile
+  static constexpr int LPG = K * NTL;                // lanes per group
+  static constexpr int G = kBatchLines / LPG;        // groups
+};
+
 template <int K, int D, typename T>
 struct BatchWork {
   static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false),
                        RS = LineShape<K, D>::RS, RP = BatchShape<K, D>::RP;
   T tab[TabOff::size(K)];
   T U[ME][ND];
-  T OUT[ME][ND];
+  double OUT[ME][ND];  // the cells' rows of v (double also for T = float)
   T REC[kBatchLines * LineShape<K, D>::RSP];  // the round's records
   int rec[batch_record_ints(ME)];
 };
@@ -1054,32 +1073,59 @@ __device__ __forceinline__ void reduce_axis_2d(const T* REC, int lo, int hi, con
 // 3D: OUT += the records [lo, hi) of the round, all along axis KA (group
 // reduction described above)
 template <int K, int KA, typename T>
-__device__ __forceinline__ void reduce_axis_3d(const T* REC, int lo, int hi, T* OUT) {
+__device__ __forceinline__ void reduce_axis_3d(const T* REC, int lo, int hi, double* OUT) {
   using LS = LineShape<K, 3>;
-  constexpr int KK = K * K, G = kBatchLines / KK;
+  using RS = ReduceShape<K>;
+  constexpr int A = RS::A, G = RS::G, LPG = RS::LPG;
   constexpr int O1 = KA == 0 ? 1 : 0;
   constexpr int O2 = KA == 2 ? 1 : 2;
   constexpr int SK = ipow(K, KA), S1 = ipow(K, O1), S2 = ipow(K, O2);
-  const int t = threadIdx.x, grp = t / KK, m = t % KK, i1 = m / K, ik = m % K;
-  if (grp >= G || lo >= hi) return;
-  T acc[K];
+  const int t = threadIdx.x, grp = t / LPG, m = t % LPG, ik = m % K, i1b = (m / K) * A;
+  if (grp >= G || lo + grp >= hi) return;
+  // rows of the lane's tile (the last tile may be short) and the rotations
+  const int na = RS::NTL == 1 ? A : min(A, K - i1b);
+  const int rot2 = grp % K, rot1 = RS::NTL == 1 ? (grp / K) % A : 0;
+  int o1[A], o2[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) acc[i] = 0;
+  for (int s1 = 0; s1 < A; ++s1) o1[s1] = i1b + (s1 + rot1 < A ? s1 + rot1 : s1 + rot1 - A);
+#pragma unroll
+  for (int s2 = 0; s2 < K; ++s2) o2[s2] = s2 + rot2 < K ? s2 + rot2 : s2 + rot2 - K;
+  T acc[A][K];
+#pragma unroll
+  for (int s1 = 0; s1 < A; ++s1)
+#pragma unroll
+    for (int s2 = 0; s2 < K; ++s2) acc[s1][s2] = 0;
   for (int r = lo + grp; r < hi; r += G) {
     const T* R = REC + r * LS::RSP;
-    const T v1 = R[LS::V1 + i1];
-    const T pp = v1 * R[LS::D0 + ik] + R[LS::DV1 + i1] * R[LS::D1 + ik];
-    const T qq = v1 * R[LS::D2 + ik];
-    // V2, dV2: the same for the whole group, consecutive in the record
+    const T d0 = R[LS::D0 + ik], d1 = R[LS::D1 + ik], d2 = R[LS::D2 + ik];
+    T v2[K], w2[K];
 #pragma unroll
-    for (int i2 = 0; i2 < K; ++i2) acc[i2] += R[LS::V2 + i2] * pp + R[LS::DV2 + i2] * qq;
+    for (int s2 = 0; s2 < K; ++s2) {
+      v2[s2] = R[LS::V2 + o2[s2]];
+      w2[s2] = R[LS::DV2 + o2[s2]];
+    }
+#pragma unroll
+    for (int s1 = 0; s1 < A; ++s1) {
+      if (RS::NTL > 1 && s1 >= na) break;
+      const T v1 = R[LS::V1 + o1[s1]];
+      const T pp = v1 * d0 + R[LS::DV1 + o1[s1]] * d1;
+      const T qq = v1 * d2;
+#pragma unroll
+      for (int s2 = 0; s2 < K; ++s2) {
+        acc[s1][s2] += v2[s2] * pp;
+        acc[s1][s2] += w2[s2] * qq;
+      }
+    }
   }
-  // the groups meet in the cell's row through LDS atomic adds
-  T* row = OUT + ik * SK + i1 * S1;
 #pragma unroll
-  for (int i2 = 0; i2 < K; ++i2) {
-    if constexpr (G == 1) row[i2 * S2] += acc[i2];
-    else atomicAdd(row + i2 * S2, acc[i2]);
+  for (int s1 = 0; s1 < A; ++s1) {
+    if (RS::NTL > 1 && s1 >= na) break;
+    double* row = OUT + ik * SK + o1[s1] * S1;
+#pragma unroll
+    for (int s2 = 0; s2 < K; ++s2) {
+      if constexpr (G == 1) row[o2[s2] * S2] += acc[s1][s2];
+      else atomicAdd(row + o2[s2] * S2, (double)acc[s1][s2]);
+    }
   }
 }
 
@@ -1152,7 +1198,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
         const int a0 = ent[4 * e + 2] & OFS, a3 = e + 1 < ne ? (ent[4 * (e + 1) + 2] & OFS) : total;
         if (a0 >= r1 || a3 <= base) continue;
         const int a1 = a0 + (ent[4 * e + 1] & 0xffff), a2 = a1 + ((ent[4 * e + 1] >> 16) & 0xffff);
-        T* out = &W.OUT[0][0] + e * ND;
+        double* out = &W.OUT[0][0] + e * ND;
         if constexpr (D == 3) {
           reduce_axis_3d<K, 0>(W.REC, max(a0, base) - base, min(a1, r1) - base, out);
           reduce_axis_3d<K, 1>(W.REC, max(a1, base) - base, min(a2, r1) - base, out);
@@ -1172,7 +1218,7 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
     }
     for (int idx = t; idx < ne * ND; idx += NT) {
       const int e = idx / ND, l = idx % ND;
-      v[(int64_t)ent[4 * e] * ND + l] = W.OUT[e][l];
+      v[(int64_t)ent[4 * e] * ND + l] = (T)W.OUT[e][l];
     }
   }
 }
