@@ -103,6 +103,22 @@ std::vector<double> make_tables(const ufem::Plan& P) {
       }
     for (int i = 0; i < K; ++i) t[ufem::TabOff::DS(K) + q * K + i] = dl[K + i];
   }
+  // ghost penalty of a face, folded over the derivative orders j
+  for (int s = 0; s < 2; ++s) {
+    const double* Eo = &t[s ? ufem::TabOff::E1(K) : ufem::TabOff::E0(K)];
+    const double* En = &t[s ? ufem::TabOff::E0(K) : ufem::TabOff::E1(K)];
+    for (int l = 0; l < K; ++l)
+      for (int m = 0; m < K; ++m) {
+        double oo = 0, on = 0;
+        for (int j = 0; j < K; ++j) {
+          const double g = t[ufem::TabOff::GW(K) + j] * Eo[j * K + l];
+          oo += g * Eo[j * K + m];
+          on += g * En[j * K + m];
+        }
+        t[ufem::TabOff::GP(K) + (2 * s) * K * K + l * K + m] = oo;
+        t[ufem::TabOff::GP(K) + (2 * s + 1) * K * K + l * K + m] = on;
+      }
+  }
   return t;
 }
 

@@ -27,6 +27,11 @@ constexpr int kFlagNoVolume = 24;
 //   M [K*K]   1D mass matrix of the GLL Lagrange basis (exact: Gauss rule)
 //   KS[K*K]   1D stiffness matrix of the GLL Lagrange basis
 //   DS[K*K]   DS[q*K+i] = L_i'(g_q), GLL basis derivative at the Gauss points
+//   GP[4*K*K] face ghost penalty of a face on side s (0: lower, 1: upper) of
+//             the own cell, GP[(2s+n)*K*K + l*K + m] = sum_j gamma_j E^j_l
+//             F^j_m with E the own basis derivatives at the face and F = E
+//             (n = 0) or the neighbour's (n = 1)
+// (kernels that stage the table in LDS copy its first lds_size(K) entries)
 // Line batches of the cut-cell kernels.  Batch b has a record of
 // batch_record_ints(ME) ints at a fixed stride: (entries, lines, offset of
 // its descriptors beyond the first kBatchLines in the overflow area, 0), then
@@ -40,9 +45,11 @@ constexpr int kFlagNoVolume = 24;
 // volume / interface entries (slot 15), in-face axes for cut-face entries
 // (one per cut face of a cut cell).  Entries of one cell are consecutive and
 // in one batch.
-// entries (one per cell, or per cut face of a cell) and cells of a batch
+// entries (one per cell, or per cut face of a cell) and cells of a batch (a
+// cut cell has at least 2 k^(d-1) volume and interface lines, so a batch of
+// 64 lines rarely holds more volume entries than these)
 constexpr __host__ __device__ int batch_max_entries(int nd, bool face) {
-  return face ? (nd <= 64 ? 12 : 6) : (nd <= 64 ? 8 : (nd <= 125 ? 4 : 1));
+  return face ? (nd <= 64 ? 12 : 6) : (nd <= 27 ? 8 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1)));
 }
 constexpr __host__ __device__ int batch_max_cells(int nd, bool face) {
   return face ? (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1)) : batch_max_entries(nd, false);
@@ -63,7 +70,9 @@ struct TabOff {
   static __host__ __device__ constexpr int M(int K) { return 4 * K * K + 4 * K; }
   static __host__ __device__ constexpr int KS(int K) { return 5 * K * K + 4 * K; }
   static __host__ __device__ constexpr int DS(int K) { return 6 * K * K + 4 * K; }
-  static __host__ __device__ constexpr int size(int K) { return 7 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int GP(int K) { return 7 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int lds_size(int K) { return 7 * K * K + 4 * K; }
+  static __host__ __device__ constexpr int size(int K) { return 11 * K * K + 4 * K; }
 };
 
 template <typename T>

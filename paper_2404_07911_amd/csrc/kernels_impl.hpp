@@ -208,15 +208,19 @@ __device__ __forceinline__ void line_faces(const T* __restrict__ tab, const DevA
       for (int l = 0; l < K; ++l) R[l] += Eo[l] * cv + Eo[K + l] * cd;
     }
     if (fg) {
-      const T* GW = tab + TabOff::GW(K);
+      // sum_j gamma_j E^j_l (d^j u_own - d^j u_nb), folded into two K x K
+      // matrices on the host
+      const T* Go = tab + TabOff::GP(K) + 2 * side * K * K;
+      const T* Gn = Go + K * K;
 #pragma unroll
-      for (int jj = 0; jj < K; ++jj) {
-        T dj = 0;
+      for (int l = 0; l < K; ++l) {
+        T r = R[l];
 #pragma unroll
-        for (int l = 0; l < K; ++l) dj += Eo[jj * K + l] * uo[l] - En[jj * K + l] * un[l];
-        dj *= GW[jj];
-#pragma unroll
-        for (int l = 0; l < K; ++l) R[l] += Eo[jj * K + l] * dj;
+        for (int m = 0; m < K; ++m) {
+          r += Go[l * K + m] * uo[m];
+          r -= Gn[l * K + m] * un[m];
+        }
+        R[l] = r;
       }
     }
   }
@@ -1046,7 +1050,6 @@ template <int K, int D, typename T>
 struct BatchWork {
   static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false),
                        RS = LineShape<K, D>::RS, RP = BatchShape<K, D>::RP;
-  T tab[TabOff::size(K)];
   T U[ME][ND];
   double OUT[ME][ND];  // the cells' rows of v (double also for T = float)
   T REC[kBatchLines * LineShape<K, D>::RSP];  // the round's records
@@ -1139,7 +1142,6 @@ __global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __
   constexpr int OFS = (1 << kBatchOffsetBits) - 1;
   __shared__ BW W;
   const int t = threadIdx.x;
-  for (int i = t; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
   const bool do_vol = (a.terms & 1) != 0, do_surf = (a.terms & 4) != 0;
   int dof_i[NPL][3];
   lane_dofs<K, D, NPL>(dof_i);
@@ -1246,7 +1248,7 @@ template <int K, int D, typename T>
 struct FaceWork {
   static constexpr int NF = FaceShape<K, D>::NF, ME = batch_max_entries(ipow(K, D), true),
                        RS = FaceShape<K, D>::RS, RP = BatchShape<K, D>::RP;
-  T tab[TabOff::size(K)];
+  T tab[TabOff::lds_size(K)];
   T TR[ME][4][NF];  // own value, own normal derivative, neighbour value, neighbour normal derivative
   T REC[RS * RP];
   int rec[batch_record_ints(ME)];
@@ -1361,7 +1363,7 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
   constexpr int OFS = (1 << kBatchOffsetBits) - 1;
   __shared__ FW W;
   const int t = threadIdx.x;
-  for (int i = t; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
+  for (int i = t; i < TabOff::lds_size(K); i += NT) W.tab[i] = a.tab[i];
   int dof_i[NPL][3];
   lane_dofs<K, D, NPL>(dof_i);
   BatchFetch nxt = batch_fetch<ME>(brec, desc, blockIdx.x, n_batches);
@@ -1810,7 +1812,7 @@ __device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int i
 template <int K, int D, typename T, bool FACE>
 struct DkBatchWork {
   static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), FACE);
-  T tab[TabOff::size(K)];
+  T tab[TabOff::lds_size(K)];
   T Wo[ME][ND];
   T Yo[ME][ND];
   T Wn[FACE ? ME : 1][FACE ? ND : 1];
@@ -1825,7 +1827,7 @@ __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __res
   using BW = DkBatchWork<K, D, T, FACE>;
   constexpr int ND = BW::ND, ME = BW::ME, NT = 64, NR = batch_record_ints(ME);
   __shared__ BW W;
-  for (int i = threadIdx.x; i < TabOff::size(K); i += NT) W.tab[i] = a.tab[i];
+  for (int i = threadIdx.x; i < TabOff::lds_size(K); i += NT) W.tab[i] = a.tab[i];
   const int t = threadIdx.x;
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     if (t < NR) W.rec[t] = brec[(int64_t)b * NR + t];
