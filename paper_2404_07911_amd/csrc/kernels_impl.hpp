@@ -1451,6 +1451,56 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
       }  // (records past total are not read)
       sync();
       const int r1 = min(total, base + NT);
+      // per entry, the test coefficients of its lines in this round on the
+      // face-node grid f = iA + K iB: P0 (value) and P1 (normal derivative),
+      // P0[f] = sum over lines along A of VF[iB] D0[iA] + along B of VF[iA]
+      // D0[iB] (P1 with DN); lane (slot, f), SL entries per pass
+      constexpr int SL = NT / NF, NPS = (ME + SL - 1) / SL;
+      static_assert(2 * ME * NF <= RS * RP, "entry matrices must fit in the record area");
+      T p0[NPS], p1[NPS];
+      {
+        const int sl = t / NF, f = t % NF, fa = f % K, fb = D == 3 ? f / K : 0;
+#pragma unroll
+        for (int ps = 0; ps < NPS; ++ps) {
+          p0[ps] = 0;
+          p1[ps] = 0;
+          const int e = ps * SL + sl;
+          if (sl >= SL || e >= ne) continue;
+          const int lo0 = ent[4 * e + 2] & OFS;
+          const int hi1 = e + 1 < ne ? (ent[4 * (e + 1) + 2] & OFS) : total;
+          const int nA = ent[4 * e + 1] & 0xffff;
+#pragma unroll
+          for (int grp = 0; grp < (D == 3 ? 2 : 1); ++grp) {
+            const int lo = grp == 0 ? lo0 : lo0 + nA;
+            const int hi = grp == 0 ? lo0 + nA : hi1;
+            const int rlo = max(lo, base) - base, rhi = min(hi, r1) - base;
+            const int il = grp == 0 ? fa : fb, iF = grp == 0 ? fb : fa;
+            const T* Rv = W.REC + (FS::VF + iF) * RP;
+            const T* R0 = W.REC + (FS::D0 + il) * RP;
+            const T* Rn = W.REC + (FS::DN + il) * RP;
+            for (int rr = rlo; rr < rhi; ++rr) {
+              const T vf = D == 3 ? Rv[rr] : T(1);
+              p0[ps] += vf * R0[rr];
+              p1[ps] += vf * Rn[rr];
+            }
+          }
+        }
+      }
+      sync();  // the records are read: the matrices go into their place
+      T* PM = W.REC;  // [entry][2][NF]
+      {
+        const int sl = t / NF, f = t % NF;
+#pragma unroll
+        for (int ps = 0; ps < NPS; ++ps) {
+          const int e = ps * SL + sl;
+          if (sl < SL && e < ne) {
+            PM[(2 * e) * NF + f] = p0[ps];
+            PM[(2 * e + 1) * NF + f] = p1[ps];
+          }
+        }
+      }
+      sync();
+      // each lane adds E[iN] P0[f] + E'[iN] P1[f] to its DoFs (iN, iA, iB)
       int c = -1, prev = -1;
       for (int e = 0; e < ne; ++e) {
         const int rank = ent[4 * e];
@@ -1462,33 +1512,16 @@ __global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __r
         const int hi1 = e + 1 < ne ? (ent[4 * (e + 1) + 2] & OFS) : total;
         if (lo0 >= r1 || hi1 <= base) continue;
         const int sl = ent[4 * e + 2] >> kBatchOffsetBits, N = sl >> 1;
-        const int nA = ent[4 * e + 1] & 0xffff;
         const int A = N == 0 ? 1 : 0, B = N == 2 ? 1 : 2;
         const T* E = W.tab + ((sl & 1) ? TabOff::E1(K) : TabOff::E0(K));
+        const T* P0 = PM + (2 * e) * NF;
+        const T* P1 = P0 + NF;
         T s[NPL];
 #pragma unroll
-        for (int j = 0; j < NPL; ++j) s[j] = 0;
-#pragma unroll
-        for (int grp = 0; grp < (D == 3 ? 2 : 1); ++grp) {
-          const int lo = grp == 0 ? lo0 : lo0 + nA;
-          const int hi = grp == 0 ? lo0 + nA : hi1;
-          const int rlo = max(lo, base) - base, rhi = min(hi, r1) - base;
-          if (rlo >= rhi) continue;
-          const int LA = grp == 0 ? A : B, FA = grp == 0 ? B : A;
-#pragma unroll
-          for (int j = 0; j < NPL; ++j) {
-            auto pick = [&](int ax) { return ax == 0 ? dof_i[j][0] : (ax == 1 ? dof_i[j][1] : dof_i[j][2]); };
-            const int iN = pick(N), il = pick(LA), iF = pick(FA);
-            const T en = E[iN], den = E[K + iN];
-            const T* Rv = W.REC + (FS::VF + iF) * RP;
-            const T* R0 = W.REC + (FS::D0 + il) * RP;
-            const T* Rn = W.REC + (FS::DN + il) * RP;
-#pragma unroll 2
-            for (int rr = rlo; rr < rhi; ++rr) {
-              const T w = en * R0[rr] + den * Rn[rr];
-              s[j] += D == 3 ? Rv[rr] * w : w;
-            }
-          }
+        for (int j = 0; j < NPL; ++j) {
+          auto pick = [&](int ax) { return ax == 0 ? dof_i[j][0] : (ax == 1 ? dof_i[j][1] : dof_i[j][2]); };
+          const int iN = pick(N), f = pick(A) + (D == 3 ? K * pick(B) : 0);
+          s[j] = E[iN] * P0[f] + E[K + iN] * P1[f];
         }
 #pragma unroll
         for (int cc = 0; cc < MC; ++cc)
