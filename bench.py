@@ -204,7 +204,8 @@ def solve_mode(args, wl, rng, plan, op, t_setup):
         "n_gpus": 1,
         "dtype": "f64/f32",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: 3D SIPG DG p={wl.degree}, {wl.n}^3 background cells, ball r=0.8",
+        "config": {"workload": f"{wl.name}: {wl.dim}D SIPG DG p={wl.degree}, {wl.n}^{wl.dim} background cells, "
+                               f"{len(wl.radii)} ball(s)" + (", kappa field" if wl.name == "kappa3d" else ""),
                    "active_dofs": n, "degree": wl.degree, "background_cells": wl.n},
         "fp64_cg": {"seconds": t64, "iterations": i64["iterations"], "rel_residual": res64,
                     "converged": i64["converged"]},
