@@ -1713,7 +1713,7 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
         g[k2] = s2;
       }
       const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
-      dk[a.seg[2] + (int64_t)fi * NF + f] = wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]);
+      dk[a.seg[2] + (int64_t)a.sf_id[fi] * NF + f] = wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]);
     }
     sync();
   }
@@ -1933,6 +1933,7 @@ __global__ void __launch_bounds__(64) cut_face_dk_kernel(DevArgs<T> a, const T* 
       const int idx = min(t + NT * it, ne * NF - 1);
       const int e = idx / NF, o = idx % NF;
       const int sl = ent[4 * e + 2] >> kBatchOffsetBits, N = sl >> 1;
+      if ((sl & 1) == 0) continue;  // the upper cell of the face: no points to write
       const int ia = o / (D == 3 ? K : 1), ib = D == 3 ? o % K : 0;
       int sN, off;
       if constexpr (D == 3) {
