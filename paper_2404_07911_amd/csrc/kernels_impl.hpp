@@ -459,7 +459,7 @@ __device__ __forceinline__ T face_transform(const T* __restrict__ M1, const T* F
 }
 
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) kappa_struct_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 2 : 1))) kappa_struct_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                           const int32_t* __restrict__ kinfo,
                                                           const int64_t* __restrict__ kface, int n_list,
                                                           int with_volume) {
@@ -493,19 +493,25 @@ __global__ void __launch_bounds__(64) kappa_struct_kernel(DevArgs<T> a, const T*
     const int nbr[6] = {k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
     const int bx = line_base<K, D, 0>(l), by = line_base<K, D, 1>(l);
     const int bz = D == 3 ? line_base<K, D, 2>(l) : 0;
-    T ux[K], nb[2 * D][K];
-    int64_t fko[2 * D];
+    T ux[K];
+    // float: every neighbour line and face offset loaded up front (enough
+    // registers); double: one normal axis at a time in the face loop
+    constexpr bool kRoll = sizeof(T) == 8;
+    T nball[kRoll ? 1 : 2 * D][K];
+    int64_t fkall[kRoll ? 1 : 2 * D];
     if (valid) {
       glb_line_load<K, D, 0>(x + (int64_t)r * ND, bx, ux);
+      if constexpr (!kRoll) {
 #pragma unroll
-      for (int s = 0; s < 2 * D; ++s) {
-        fko[s] = kface[(int64_t)ci * 2 * D + s];
-        if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
-        const T* un = x + (int64_t)nbr[s] * ND;
-        const int ax = s >> 1;
-        if (ax == 0) glb_line_load<K, D, 0>(un, bx, nb[s]);
-        else if (ax == 1) glb_line_load<K, D, 1>(un, by, nb[s]);
-        else if constexpr (D == 3) glb_line_load<K, D, 2>(un, bz, nb[s]);
+        for (int s = 0; s < 2 * D; ++s) {
+          fkall[s] = kface[(int64_t)ci * 2 * D + s];
+          if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+          const T* un = x + (int64_t)nbr[s] * ND;
+          const int ax = s >> 1;
+          if (ax == 0) glb_line_load<K, D, 0>(un, bx, nball[s]);
+          else if (ax == 1) glb_line_load<K, D, 1>(un, by, nball[s]);
+          else if constexpr (D == 3) glb_line_load<K, D, 2>(un, bz, nball[s]);
+        }
       }
     }
     T* U = W.U[cc];
@@ -632,15 +638,50 @@ __global__ void __launch_bounds__(64) kappa_struct_kernel(DevArgs<T> a, const T*
       }
       sync();
     }
-    // ---- faces, one normal axis at a time; lane l is face node / Gauss
-    // point l of the face (lower in-face axis fastest)
-#pragma unroll
+    // ---- faces, one normal axis at a time (double: a loop that is not
+    // unrolled, holding one axis's neighbour lines and face terms only); lane
+    // l is face node / Gauss point l of the face (lower in-face axis fastest)
+#pragma unroll(kRoll ? 1 : D)
     for (int ax = 0; ax < D; ++ax) {
+      // this lane's line along ax: LDS positions, global offset and stride
+      int pa[K];
+      {
+        const int la = l % K, lb = D == 3 ? l / K : 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+          pa[q] = D == 2 ? (ax == 0 ? KronLayout<K, D>::at(q, l, 0) : KronLayout<K, D>::at(l, q, 0))
+                         : (ax == 0 ? KronLayout<K, D>::at(q, la, lb)
+                                    : (ax == 1 ? KronLayout<K, D>::at(la, q, lb) : KronLayout<K, D>::at(la, lb, q)));
+      }
+      const int gbase = ax == 0 ? bx : (ax == 1 ? by : bz);
+      const int gstride = ax == 0 ? 1 : (ax == 1 ? K : K * K);
+      T nbl[2][K];
+      int64_t fko[2];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int s = 2 * ax + side;
+        if constexpr (!kRoll) {
+          fko[side] = fkall[s];
+#pragma unroll
+          for (int q = 0; q < K; ++q) nbl[side][q] = nball[s][q];
+          continue;
+        }
+        fko[side] = 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) nbl[side][q] = 0;
+        if (!valid) continue;
+        fko[side] = kface[(int64_t)ci * 2 * D + s];
+        if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+        const int ns = s == 0 ? nbr[0] : s == 1 ? nbr[1] : s == 2 ? nbr[2] : s == 3 ? nbr[3] : s == 4 ? nbr[4] : nbr[5];
+        const T* un = x + (int64_t)ns * ND + gbase;
+#pragma unroll
+        for (int q = 0; q < K; ++q) nbl[side][q] = un[q * gstride];
+      }
       T R[K];
 #pragma unroll
       for (int q = 0; q < K; ++q) R[q] = 0;
       T uo[K];
-      if (valid) kl_load<K>(U, pos[ax], uo);
+      if (valid) kl_load<K>(U, pa, uo);
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const int s = 2 * ax + side;
@@ -650,7 +691,7 @@ __global__ void __launch_bounds__(64) kappa_struct_kernel(DevArgs<T> a, const T*
         const T* Eo = tab + (side ? TabOff::E1(K) : TabOff::E0(K));
         const T* En = tab + (side ? TabOff::E0(K) : TabOff::E1(K));
         const T sigma = side ? T(1) : T(-1);
-        const T* un = nb[s];
+        const T* un = nbl[side];
         // ghost penalty: derivative jumps of every order, exact in-face mass
         // (skipped by waves without such a face on this slot)
         if (__any(fg)) {
@@ -695,7 +736,7 @@ __global__ void __launch_bounds__(64) kappa_struct_kernel(DevArgs<T> a, const T*
           const T Av = face_transform<K, D, false>(S, W.F1[cc], l);
           const int q0 = l % K, q1 = D == 3 ? l / K : 0;
           T cq = a.hs * Wg[q0] * (D == 3 ? Wg[q1] : T(1));
-          if (a.kappa) cq *= a.kappa[fko[s] + l];
+          if (a.kappa) cq *= a.kappa[fko[side] + l];
           fv = cq * sigma * (a.gamma * J - Av);
           fd = T(-0.5) * cq * J;
         }
@@ -714,10 +755,10 @@ __global__ void __launch_bounds__(64) kappa_struct_kernel(DevArgs<T> a, const T*
         sync();
       }
       if (valid) {
-        kl_load<K>(OUT, pos[ax], t0);
+        kl_load<K>(OUT, pa, t0);
 #pragma unroll
         for (int q = 0; q < K; ++q) t0[q] += R[q];
-        kl_store<K>(OUT, pos[ax], t0);
+        kl_store<K>(OUT, pa, t0);
       }
       sync();
     }
