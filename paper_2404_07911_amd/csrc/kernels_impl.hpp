@@ -458,6 +458,8 @@ __device__ __forceinline__ T face_transform(const T* __restrict__ M1, const T* F
   }
 }
 
+// (up to K = 5 the kernel fits two waves per SIMD, in double with at most a
+// couple of spilled registers; beyond, the spills would cost more)
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 2 : 1))) kappa_struct_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                           const int32_t* __restrict__ kinfo,
@@ -1173,8 +1175,11 @@ __device__ __forceinline__ void reduce_axis_3d(const T* REC, int lo, int hi, dou
   }
 }
 
+// (K = 5, 6: two waves per SIMD at the price of a few spilled registers is
+// faster than one wave without, by 6 and 10 % measured; for K >= 7 the
+// spills outweigh it)
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) cut_batch_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 5 || K == 6 ? 2 : 1))) cut_batch_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                        const int32_t* __restrict__ brec,
                                                        const int32_t* __restrict__ desc, int n_batches) {
   using BW = BatchWork<K, D, T>;
