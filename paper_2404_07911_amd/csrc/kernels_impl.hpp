@@ -1397,8 +1397,11 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
   }
 }
 
+// (double, K >= 7: two waves per SIMD with a few spilled registers beat one
+// wave, 18 % at K = 7 measured)
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K >= 7 ? 2 : 1)))
+cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                       const int32_t* __restrict__ brec,
                                                       const int32_t* __restrict__ desc, int n_batches) {
   using FW = FaceWork<K, D, T>;
@@ -1956,8 +1959,10 @@ struct FaceDkWork {
   int rec[batch_record_ints(ME)];
 };
 
+// (double, K = 8: two waves per SIMD at the price of a few spilled registers)
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) cut_face_dk_kernel(DevArgs<T> a, const T* __restrict__ w,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K == 8 ? 2 : 1)))
+cut_face_dk_kernel(DevArgs<T> a, const T* __restrict__ w,
                                                          const T* __restrict__ u, T* __restrict__ dk,
                                                          const int32_t* __restrict__ brec,
                                                          const int32_t* __restrict__ desc, int n_batches) {
