@@ -56,7 +56,10 @@ enum {
 };
 
 /* Arithmetic of an apply: every input, table, quadrature datum and
- * accumulation is in this precision. */
+ * accumulation is in this precision, with one exception: the last sum of a
+ * cut cell's volume and interface line contributions into the cell's row
+ * (the rows are kept in float64 in shared memory for both precisions, where
+ * float64 atomic adds are the cheap ones). */
 enum { UFEM_F64 = 0, UFEM_F32 = 1 };
 
 /* Kernel stages of one apply (ufem_apply_part).  Stage 1 writes the rows of
