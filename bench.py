@@ -242,8 +242,8 @@ def main(argv=None):
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(
-            "bench.py measures one GPU only: this build has no multi-GPU path "
-            "(the sharding design is described in DESIGN.md); run with --gpus 1",
+            "bench.py measures one GPU only: the operator has no multi-GPU path "
+            "(each GPU would own a block of cells and exchange a halo of face data); run with --gpus 1",
             file=sys.stderr,
         )
         return 2
