@@ -1622,7 +1622,7 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
   const int c = lane / NL, l = lane % NL;
   const bool active = c < C;
   const int cc = active ? c : 0;
-  for (int c0 = blockIdx.x * C; c0 < a.n_inside; c0 += gridDim.x * C) {
+  for (int c0 = xcd_block() * C; c0 < a.n_inside; c0 += gridDim.x * C) {
     const int ci = c0 + c;
     const bool valid = active && ci < a.n_inside;
     const int r = valid ? a.inside[ci] : 0;
@@ -1719,7 +1719,7 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
   const int c = lane / NF, f = lane % NF;
   const bool active = c < C;
   const int cc = active ? c : 0;
-  for (int f0 = blockIdx.x * C; f0 < a.n_sfaces; f0 += gridDim.x * C) {
+  for (int f0 = xcd_block() * C; f0 < a.n_sfaces; f0 += gridDim.x * C) {
     const int fi = f0 + c;
     const bool valid = active && fi < a.n_sfaces;
     if (valid) {
