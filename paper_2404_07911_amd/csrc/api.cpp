@@ -135,8 +135,7 @@ struct ufem_op {
   int32_t* inside = nullptr;
   int64_t *kface_inside = nullptr, *kface_cut = nullptr;
   int32_t *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr, *fdesc = nullptr, *kinfo_inside = nullptr,
-          *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr,
-          *sf_id = nullptr;
+          *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   // per-precision data
   struct Prec {
@@ -227,7 +226,6 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.sf_bm = sf_bm;
   a.sf_bp = sf_bp;
   a.sf_ax = sf_ax;
-  a.sf_id = sf_id;
   a.n_sfaces = n_sfaces;
   a.vol_x = (const T*)d.vol_x;
   a.vol_w = (const T*)d.vol_w;
@@ -515,22 +513,15 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       desc = std::move(slots);
       desc.insert(desc.end(), ovf.begin(), ovf.end());
     };
-    // structured faces grouped by normal axis (kappa order within an axis),
-    // with their index in kappa order
-    std::vector<int32_t> sbm, sbp, sax, sid;
-    for (int ax = 0; ax < dim; ++ax) {
-      int32_t k = 0;
-      for (const ufem::Face& f : P.faces)
-        if (f.kind == ufem::kFaceStructured) {
-          if (f.axis == ax) {
-            sbm.push_back(P.rank[f.bm]);
-            sbp.push_back(P.rank[f.bp]);
-            sax.push_back(f.axis);
-            sid.push_back(k);
-          }
-          ++k;
-        }
-    }
+    // structured faces in kappa order (by lower cell, then axis: the faces
+    // of a wave share cells)
+    std::vector<int32_t> sbm, sbp, sax;
+    for (const ufem::Face& f : P.faces)
+      if (f.kind == ufem::kFaceStructured) {
+        sbm.push_back(P.rank[f.bm]);
+        sbp.push_back(P.rank[f.bp]);
+        sax.push_back(f.axis);
+      }
     op->n_sfaces = (int32_t)sbm.size();
     // per-position cell info of the Kronecker kernel's lists
     auto make_kinfo = [&](const std::vector<int32_t>& list) {
@@ -584,7 +575,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
         (rc = op->upload((void**)&op->fbrec, fb)) || (rc = op->upload((void**)&op->fdesc, fl)) ||
         (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||
-        (rc = op->upload((void**)&op->sf_ax, sax)) || (rc = op->upload((void**)&op->sf_id, sid))) {
+        (rc = op->upload((void**)&op->sf_ax, sax))) {
       delete op;
       return rc;
     }

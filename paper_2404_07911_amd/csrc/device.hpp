@@ -95,12 +95,10 @@ struct DevArgs {
   const int32_t* fdesc;
   int32_t n_vbatch, n_fbatch;
   int32_t n_cu;  // compute units of the device (persistent grids)
-  // structured SIPG faces grouped by normal axis: ranks of the lower / upper
-  // cell, axis
+  // structured SIPG faces (kappa order): ranks of the lower / upper cell, axis
   const int32_t* sf_bm;
   const int32_t* sf_bp;
   const int32_t* sf_ax;
-  const int32_t* sf_id;  // (grouped by axis; index of the face in kappa order)
   int32_t n_sfaces;
   const T* vol_x;            // SoA: vol_x[a * n_vol + q]
   const T* vol_w;

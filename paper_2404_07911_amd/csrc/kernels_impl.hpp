@@ -1764,7 +1764,7 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
         g[k2] = s2;
       }
       const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
-      dk[a.seg[2] + (int64_t)a.sf_id[fi] * NF + f] = wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]);
+      dk[a.seg[2] + (int64_t)fi * NF + f] = wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]);
     }
     sync();
   }
