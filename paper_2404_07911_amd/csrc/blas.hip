@@ -62,17 +62,16 @@ __device__ __forceinline__ double block_sum(double s) {
   return red[0];
 }
 
-// x += alpha p, r -= alpha Ap, new r.r; alpha = r.r / p.Ap
+// r -= alpha Ap, new r.r; alpha = r.r / p.Ap (x is updated with the old p
+// by the direction kernel, which reads p anyway)
 template <typename T>
-__global__ void __launch_bounds__(256) cg_update_kernel(int64_t n, T* __restrict__ x, T* __restrict__ r,
-                                                        const T* __restrict__ p, const T* __restrict__ ap,
+__global__ void __launch_bounds__(256) cg_update_kernel(int64_t n, T* __restrict__ r, const T* __restrict__ ap,
                                                         double* __restrict__ scal) {
   const double pap = scal[1];
   if (scal[3] != 0.0 || !(pap > 0.0)) return;
   const T alpha = (T)(scal[0] / pap);
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
     const T ri = r[i] - alpha * ap[i];
     r[i] = ri;
     s += (double)ri * (double)ri;
@@ -81,14 +80,18 @@ __global__ void __launch_bounds__(256) cg_update_kernel(int64_t n, T* __restrict
   if (threadIdx.x == 0) atomicAdd(scal + 2, bs);
 }
 
-// p = r + beta p, beta = new r.r / r.r
+// x += alpha p, then p = r + beta p; beta = new r.r / r.r
 template <typename T>
-__global__ void __launch_bounds__(256) cg_direction_kernel(int64_t n, const T* __restrict__ r, T* __restrict__ p,
-                                                           const double* __restrict__ scal) {
+__global__ void __launch_bounds__(256) cg_direction_kernel(int64_t n, T* __restrict__ x, const T* __restrict__ r,
+                                                           T* __restrict__ p, const double* __restrict__ scal) {
   if (scal[3] != 0.0 || !(scal[1] > 0.0)) return;
+  const T alpha = (T)(scal[0] / scal[1]);
   const T beta = (T)(scal[2] / scal[0]);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = r[i] + beta * p[i];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T pi = p[i];
+    x[i] += alpha * pi;
+    p[i] = r[i] + beta * pi;
+  }
 }
 
 // next iteration's scalars (one thread); a non-positive p.Ap stops the loop
@@ -109,12 +112,12 @@ hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const 
   if (n > 0) {
     if (prec == 0) {
       dot_kernel<double><<<g, 256, 0, s>>>(n, (const double*)p, (const double*)ap, scal + 1);
-      cg_update_kernel<double><<<g, 256, 0, s>>>(n, (double*)x, (double*)r, (const double*)p, (const double*)ap, scal);
-      cg_direction_kernel<double><<<g, 256, 0, s>>>(n, (const double*)r, (double*)p, scal);
+      cg_update_kernel<double><<<g, 256, 0, s>>>(n, (double*)r, (const double*)ap, scal);
+      cg_direction_kernel<double><<<g, 256, 0, s>>>(n, (double*)x, (const double*)r, (double*)p, scal);
     } else {
       dot_kernel<float><<<g, 256, 0, s>>>(n, (const float*)p, (const float*)ap, scal + 1);
-      cg_update_kernel<float><<<g, 256, 0, s>>>(n, (float*)x, (float*)r, (const float*)p, (const float*)ap, scal);
-      cg_direction_kernel<float><<<g, 256, 0, s>>>(n, (const float*)r, (float*)p, scal);
+      cg_update_kernel<float><<<g, 256, 0, s>>>(n, (float*)r, (const float*)ap, scal);
+      cg_direction_kernel<float><<<g, 256, 0, s>>>(n, (float*)x, (const float*)r, (float*)p, scal);
     }
   }
   cg_roll_kernel<<<1, 64, 0, s>>>(scal);
