@@ -227,16 +227,6 @@ __device__ __forceinline__ void line_faces(const T* __restrict__ tab, const DevA
 }
 
 template <int K, int D, int AX, typename T>
-__device__ __forceinline__ void lds_line_load(const T* arr, int base, T* v) {
-#pragma unroll
-  for (int q = 0; q < K; ++q) v[q] = arr[base + q * line_stride<K, D, AX>()];
-}
-template <int K, int D, int AX, typename T>
-__device__ __forceinline__ void lds_line_store(T* arr, int base, const T* v) {
-#pragma unroll
-  for (int q = 0; q < K; ++q) arr[base + q * line_stride<K, D, AX>()] = v[q];
-}
-template <int K, int D, int AX, typename T>
 __device__ __forceinline__ void glb_line_load(const T* __restrict__ src, int base, T* v) {
 #pragma unroll
   for (int q = 0; q < K; ++q) v[q] = src[base + q * line_stride<K, D, AX>()];
@@ -1603,10 +1593,15 @@ cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
 // sum factorisation (one lane per 1D line, as in the Kronecker kernel)
 template <int K, int D, typename T>
 struct DkWork {
-  static constexpr int ND = KronShape<K, D>::ND, C = KronShape<K, D>::C;
-  T A[2][C][ND];
-  T B[2][C][ND];
-  T E[2][C][ND];
+  // K = 3, 4: cell tensors in the skewed, padded layout of the Kronecker
+  // kernel (their plain layout had 17 bank conflicts per LDS instruction at
+  // K = 4); other K: the plain layout (K = 2: the padding would double the
+  // LDS of 16 cells per wave; K >= 5: the skew measured slower)
+  static constexpr bool SKEW = K == 3 || K == 4;
+  static constexpr int NDP = SKEW ? KronLayout<K, D>::NDP : KronLayout<K, D>::ND, C = KronShape<K, D>::C;
+  T A[2][C][NDP];
+  T B[2][C][NDP];
+  T E[2][C][NDP];
 };
 
 template <int K, int D, typename T>
@@ -1628,6 +1623,19 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
     const int r = valid ? a.inside[ci] : 0;
     const int bx = line_base<K, D, 0>(l), by = line_base<K, D, 1>(l);
     const int bz = D == 3 ? line_base<K, D, 2>(l) : 0;
+    int px[K], py[K], pz[K];
+    if constexpr (DkWork<K, D, T>::SKEW) {
+      KronLayout<K, D>::template line<0>(l, px);
+      KronLayout<K, D>::template line<1>(l, py);
+      if constexpr (D == 3) KronLayout<K, D>::template line<2>(l, pz);
+    } else {
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        px[q] = bx + q * line_stride<K, D, 0>();
+        py[q] = by + q * line_stride<K, D, 1>();
+        pz[q] = D == 3 ? bz + q * line_stride<K, D, 2>() : 0;
+      }
+    }
     T t0[K], t1[K], t2[K];
     if (valid) {
 #pragma unroll
@@ -1635,8 +1643,8 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
         glb_line_load<K, D, 0>((f ? u : w) + (int64_t)r * ND, bx, t0);
         line_mat<K>(S, t0, t1);
         line_mat<K>(DS, t0, t2);
-        lds_line_store<K, D, 0>(W.A[f][cc], bx, t1);
-        lds_line_store<K, D, 0>(W.B[f][cc], bx, t2);
+        kl_store<K>(W.A[f][cc], px, t1);
+        kl_store<K>(W.B[f][cc], px, t2);
       }
     }
     sync();
@@ -1644,14 +1652,14 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
       if (valid) {
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-          lds_line_load<K, D, 1>(W.A[f][cc], by, t0);
+          kl_load<K>(W.A[f][cc], py, t0);
           line_mat<K>(S, t0, t1);
           line_mat<K>(DS, t0, t2);
-          lds_line_store<K, D, 1>(W.A[f][cc], by, t1);  // S S u
-          lds_line_store<K, D, 1>(W.E[f][cc], by, t2);  // DS_y S_x u
-          lds_line_load<K, D, 1>(W.B[f][cc], by, t0);
+          kl_store<K>(W.A[f][cc], py, t1);  // S S u
+          kl_store<K>(W.E[f][cc], py, t2);  // DS_y S_x u
+          kl_load<K>(W.B[f][cc], py, t0);
           line_mat<K>(S, t0, t1);
-          lds_line_store<K, D, 1>(W.B[f][cc], by, t1);  // S_y DS_x u
+          kl_store<K>(W.B[f][cc], py, t1);  // S_y DS_x u
         }
       }
       sync();
@@ -1659,11 +1667,11 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
         T g[2][3][K];
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-          lds_line_load<K, D, 2>(W.A[f][cc], bz, t0);
+          kl_load<K>(W.A[f][cc], pz, t0);
           line_mat<K>(DS, t0, g[f][2]);
-          lds_line_load<K, D, 2>(W.E[f][cc], bz, t0);
+          kl_load<K>(W.E[f][cc], pz, t0);
           line_mat<K>(S, t0, g[f][1]);
-          lds_line_load<K, D, 2>(W.B[f][cc], bz, t0);
+          kl_load<K>(W.B[f][cc], pz, t0);
           line_mat<K>(S, t0, g[f][0]);
         }
         const int qx = bz % K, qy = bz / K;
@@ -1679,9 +1687,9 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
         T g[2][2][K];
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-          lds_line_load<K, D, 1>(W.A[f][cc], by, t0);
+          kl_load<K>(W.A[f][cc], py, t0);
           line_mat<K>(DS, t0, g[f][1]);
-          lds_line_load<K, D, 1>(W.B[f][cc], by, t0);
+          kl_load<K>(W.B[f][cc], py, t0);
           line_mat<K>(S, t0, g[f][0]);
         }
         const int qx = by;
