@@ -80,8 +80,13 @@ enum {
 typedef struct ufem_plan ufem_plan; /* host-side plan (no GPU) */
 typedef struct ufem_op ufem_op;     /* device-side operator */
 
+/* Level-set kinds of ufem_problem.levelset.  BALLS: a union of balls,
+ * phi = min_i (|x - c_i| - r_i) (the sphere geometries of Section 6).  PLANE:
+ * phi = (n . x - offset) / |n| (the plane benchmark of Section 5.2). */
+enum { UFEM_LEVELSET_BALLS = 0, UFEM_LEVELSET_PLANE = 1 };
+
 /* Problem description.  All pointers are host pointers read during
- * ufem_plan_create only. */
+ * ufem_plan_create only.  The physical domain is {phi < 0}. */
 typedef struct {
   int32_t dim;           /* 2 or 3 */
   int32_t n;             /* background cells per direction, >= 2 */
@@ -90,14 +95,18 @@ typedef struct {
   int32_t q_cut;         /* Gauss points per 1D piece of the cut-cell, cut-face
                             and interface rules; 0 selects p + 1 */
   int32_t max_depth;     /* subdivision limit of the cut rules; < 0 selects 4 */
-  int32_t n_balls;       /* level set phi = min_i (|x - c_i| - r_i), >= 1 */
-  const double* centers; /* host, n_balls * dim, row-major */
-  const double* radii;   /* host, n_balls, > 0 */
+  int32_t n_balls;       /* BALLS: number of balls, >= 1 (PLANE: ignored) */
+  const double* centers; /* BALLS: host, n_balls * dim, row-major */
+  const double* radii;   /* BALLS: host, n_balls, > 0 */
   double nitsche_factor; /* tau_D = nitsche_factor * p^2 (Section 2.1) */
   double sipg_factor;    /* gamma = sipg_factor * p^2, SIPG penalty gamma/h */
   double gp_gamma;       /* ghost penalty weight */
   int32_t gp_jmin;       /* lowest normal-derivative order penalised, 0..p */
   int32_t gp_flat;       /* 0: gamma_j = gp_gamma/(j!)^2, 1: gamma_j = gp_gamma */
+  int32_t levelset;      /* UFEM_LEVELSET_BALLS (0, the zero-initialised
+                            default) or UFEM_LEVELSET_PLANE */
+  double plane_normal[3];/* PLANE: normal n (first dim entries, nonzero) */
+  double plane_offset;   /* PLANE: offset; phi = (n . x - offset) / |n| */
 } ufem_problem;
 
 typedef struct {
@@ -152,8 +161,17 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
 int ufem_destroy(ufem_op* op);
 int ufem_info_op(const ufem_op* op, ufem_info* info);
 
-/* Select the terms of subsequent applies (default UFEM_TERM_ALL). */
+/* Select the terms of subsequent applies and adjoint passes (default
+ * UFEM_TERM_ALL). */
 int ufem_set_terms(ufem_op* op, int32_t term_mask);
+
+/* Cap on the workgroups of every kernel launch of subsequent calls (0, the
+ * default: each launch is sized by its work, the persistent cut-cell kernels
+ * by occupancy times compute units).  Every kernel loops over its cell
+ * groups or batches, so any cap gives the same result bit for bit; a small
+ * cap makes each workgroup take many groups in turn (used by the tests to
+ * run the multi-batch paths on small problems).  EINVAL for a negative cap. */
+int ufem_set_max_blocks(ufem_op* op, int32_t max_blocks);
 
 /* Per-quadrature-point coefficient kappa (the variable coefficient of the
  * volume, SIPG and Nitsche terms; the ghost penalty carries none).  kappa is a
@@ -161,9 +179,17 @@ int ufem_set_terms(ufem_op* op, int32_t term_mask);
  * operator on `stream`; kappa == NULL returns to kappa = 1. */
 int ufem_set_kappa(ufem_op* op, int32_t precision, const void* kappa, void* stream);
 
-/* v := A u (overwrite).  u, v: device pointers to n_dofs values of
- * `precision`; u must not overlap v (EINVAL).  Asynchronous on `stream`;
- * allocates nothing. */
+/* v := A u (overwrite): the operator action of Section 3.1 (eq.
+ * operatorevaluation), the sum over cells and faces of read, evaluate,
+ * quadrature-point operator, integrate and distribute (eq.
+ * matrixfreeopcompact) for the DG form of Section 2.1 (eq. bilinear_dg with
+ * the Nitsche terms of eq. bilinear_cg) plus the face ghost penalty; uncut
+ * cells and faces with tensor-product (structured) quadrature, cut cells,
+ * cut faces and the interface with the dimension-reduction (unstructured)
+ * quadrature of Section 3.2 (eq. unstructured_cell, unstructured_face).
+ * u, v: device pointers to n_dofs values of `precision`, cell-contiguous
+ * (layout above); u must not overlap v (EINVAL).  Every entry of v is
+ * written.  Asynchronous on `stream`; allocates nothing. */
 int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* stream);
 
 /* The kernel stages of ufem_apply (UFEM_PART_* bits, any non-empty mask),
@@ -177,15 +203,18 @@ int ufem_apply(ufem_op* op, int32_t precision, const void* u, void* v, void* str
 int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u, void* v, void* stream);
 
 /* Adjoint pass for L(kappa, u) with residual weight w:
- *   ATw := A^T w  (the transposed evaluation, integration and evaluation
- *                  swapped; A is symmetric so this equals A w),
+ *   ATw := A^T w  (the transposed operator of eq. matrixfreeopcompact, each
+ *                  cell and face term with evaluation and integration
+ *                  swapped, R^T E^T B^T I^T D^T; for the self-adjoint Poisson
+ *                  form of Section 2.1 I = E^T, so this equals A w),
  *   dkappa[q] := a_q(w, u), the contribution of quadrature point q to
  *                w^T A(kappa) u divided by kappa_q (dL/dkappa_q for
  *                L = 0.5 |A u - b|^2 with w = A u - b).
- * The term mask (ufem_set_terms) selects the terms of ATw; dkappa always
- * covers every kappa-weighted term (volume, SIPG and Nitsche points).
+ * The term mask (ufem_set_terms) selects the terms of both outputs: points
+ * of a switched-off term get dkappa = 0 (the ghost penalty carries no kappa).
  * w, u, ATw: device, n_dofs; dkappa: device, n_qp, or NULL to skip.  ATw must
- * not overlap w or u. */
+ * not overlap w or u, dkappa none of the three (EINVAL).  Asynchronous on
+ * `stream`; allocates nothing. */
 int ufem_apply_adjoint(ufem_op* op, int32_t precision, const void* w, const void* u, void* ATw,
                        void* dkappa, void* stream);
 

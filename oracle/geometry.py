@@ -3,12 +3,17 @@
 Test infrastructure only (see the package docstring).
 
 Level set (Section 6.1): a ball is phi(x) = |x - c| - R; a union of balls is
-the minimum of the ball level sets.  The physical domain is {phi < 0}.
+the minimum of the ball level sets.  The plane benchmark of Section 5.2 uses a
+plane, phi(x) = n . x - c with a unit normal n.  The physical domain is
+{phi < 0}.
 
 Cell classes (Section 2.3 and the cell categories of Section 3.4):
   inside  -- some single ball contains the closed cell box,
   outside -- every ball stays at distance >= R from the closed box,
-  cut     -- otherwise.
+  cut     -- otherwise;
+for a plane: inside if phi < 0 at every corner of the closed box, outside if
+phi >= 0 at every corner, cut otherwise (the same rule: max phi < 0 inside,
+min phi >= 0 outside).
 Active cells are inside + cut; only they carry DoFs (outside cells get
 weight 0 in the paper's load balancing, Section 3.5).
 
@@ -20,6 +25,8 @@ background index of the lower cell and then by axis.  A face is
 The ghost penalty acts on the full face whenever one of its cells is cut.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -62,9 +69,53 @@ class Balls:
         return float(np.sqrt(np.dot(near, near))), float(np.sqrt(np.dot(far, far)))
 
 
-def box_class(balls: Balls, lo, hi) -> int:
+class Plane:
+    """Half space below a plane: phi(x) = n . x - c, n of unit length (the
+    given normal and offset are scaled by 1 / |normal|)."""
+
+    def __init__(self, normal, offset):
+        nv = np.asarray(normal, dtype=np.float64).reshape(-1)
+        s = 0.0
+        for a in range(nv.size):
+            s += float(nv[a]) * float(nv[a])
+        L = math.sqrt(s)
+        if not L > 0.0:
+            raise ValueError("plane normal must be nonzero")
+        self.n = nv / L
+        self.c0 = float(offset) / L
+
+    @property
+    def m(self) -> int:
+        return 1
+
+    def psi(self, i: int, x: np.ndarray) -> float:
+        s = 0.0
+        for a in range(self.n.size):
+            s += float(self.n[a]) * float(x[a])
+        return s - self.c0
+
+    def phi(self, x: np.ndarray) -> float:
+        return self.psi(0, x)
+
+    def phi_many(self, X: np.ndarray) -> np.ndarray:
+        X = np.atleast_2d(X)
+        return X @ self.n - self.c0
+
+    def box_range(self, lo, hi):
+        """Smallest and largest phi over the box [lo, hi]."""
+        lo = np.asarray(lo, dtype=np.float64)
+        hi = np.asarray(hi, dtype=np.float64)
+        mn = float(np.sum(np.where(self.n > 0, self.n * lo, self.n * hi))) - self.c0
+        mx = float(np.sum(np.where(self.n > 0, self.n * hi, self.n * lo))) - self.c0
+        return mn, mx
+
+
+def box_class(balls, lo, hi) -> int:
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
+    if isinstance(balls, Plane):
+        mn, mx = balls.box_range(lo, hi)
+        return INSIDE if mx < 0.0 else (CUT if mn < 0.0 else OUTSIDE)
     any_touch = False
     for i in range(balls.m):
         dmin, dmax = balls.box_dist(i, lo, hi)
@@ -100,11 +151,19 @@ class Mesh:
         return lo, lo + self.h
 
 
-def classify_cells(mesh: Mesh, balls: Balls) -> np.ndarray:
+def classify_cells(mesh: Mesh, balls) -> np.ndarray:
     """Class of every background cell (vectorised over cells, loop over balls)."""
     idx = np.indices((mesh.n,) * mesh.dim).reshape(mesh.dim, -1)[::-1].T  # x fastest
     lo = mesh.lo + idx * mesh.h
     hi = lo + mesh.h
+    if isinstance(balls, Plane):
+        nv = balls.n
+        mn = np.sum(np.where(nv > 0, nv * lo, nv * hi), axis=1) - balls.c0
+        mx = np.sum(np.where(nv > 0, nv * hi, nv * lo), axis=1) - balls.c0
+        cls = np.full(mesh.n_cells, OUTSIDE, dtype=np.int8)
+        cls[mn < 0.0] = CUT
+        cls[mx < 0.0] = INSIDE
+        return cls
     inside = np.zeros(mesh.n_cells, dtype=bool)
     touch = np.zeros(mesh.n_cells, dtype=bool)
     for i in range(balls.m):
@@ -121,7 +180,7 @@ def classify_cells(mesh: Mesh, balls: Balls) -> np.ndarray:
     return cls
 
 
-def active_faces(mesh: Mesh, balls: Balls, cls: np.ndarray):
+def active_faces(mesh: Mesh, balls, cls: np.ndarray):
     """Interior faces between active cells, in canonical order.
 
     Returns a list of tuples (b_minus, b_plus, axis, kind, gp) where kind is

@@ -44,7 +44,7 @@ import math
 import numpy as np
 
 from .basis import gauss_legendre, gauss_lobatto_nodes, lagrange_derivatives
-from .geometry import CUT, INSIDE, OUTSIDE, Balls, Mesh, active_faces, classify_cells
+from .geometry import CUT, INSIDE, OUTSIDE, Balls, Mesh, Plane, active_faces, classify_cells
 from .quadrature import SayeQuadrature
 
 VOL, SIPG, NITSCHE, GP = 1, 2, 4, 8
@@ -77,6 +77,7 @@ class UnfittedDG:
         gp_gamma=0.1,
         gp_jmin=0,
         gp_weights="factorial",
+        plane=None,
     ):
         self.dim = dim
         self.p = degree
@@ -84,7 +85,9 @@ class UnfittedDG:
         self.nd = self.k**dim
         self.mesh = Mesh(dim, n, lo, hi)
         self.h = self.mesh.h
-        self.balls = Balls(centers, radii)
+        # level set: a union of balls, or with plane = (normal, offset) the
+        # half space n . x < offset of the plane benchmark
+        self.balls = Balls(centers, radii) if plane is None else Plane(plane[0], plane[1])
         self.q = self.k if q is None else q
         self.saye = SayeQuadrature(self.balls, dim, self.q, max_depth)
         self.tau = nitsche_factor * degree**2
@@ -282,10 +285,12 @@ class UnfittedDG:
         those cells are computed; the other rows stay zero."""
         return self._evaluate(u, u, mask, kappa, cells, want_dkappa=False)[0]
 
-    def dkappa(self, w, u):
+    def dkappa(self, w, u, cells=None):
         """dL/dkappa_q = a_q(w, u), the quadrature-point contribution of the
-        kappa-weighted terms to w^T A u (ghost penalty carries no kappa)."""
-        return self._evaluate(w, u, ALL, None, None, want_dkappa=True)[1]
+        kappa-weighted terms to w^T A u (ghost penalty carries no kappa).
+        With ``cells`` (background indices) only the points of those cells
+        and of the faces touching them are computed; the others stay zero."""
+        return self._evaluate(w, u, ALL, None, cells, want_dkappa=True)[1]
 
     def _block(self, vec, b):
         r = self.rank[b]
@@ -305,7 +310,7 @@ class UnfittedDG:
             return np.asarray(kappa[o : o + n], dtype=np.float64)
 
         # volume and interface terms, cell by cell
-        for b in sorted(targets if not want_dkappa else set(int(x) for x in self.active)):
+        for b in sorted(targets):
             ub = self._block(u, b)
             wb = self._block(w, b)
             if self.cls[b] == INSIDE:
@@ -344,7 +349,7 @@ class UnfittedDG:
 
         # face terms
         for fi, (bm, bp, a, kind, gp) in enumerate(self.faces):
-            if not want_dkappa and bm not in targets and bp not in targets:
+            if bm not in targets and bp not in targets:
                 continue
             um, up = self._block(u, bm), self._block(u, bp)
             wm, wp = self._block(w, bm), self._block(w, bp)

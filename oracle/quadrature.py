@@ -33,6 +33,13 @@ SPLIT problem on a box (integrate over the whole box):
   2-5 apply with every piece kept.
 
 Every rule uses q Gauss-Legendre points per one-dimensional piece.
+
+A plane level set psi = n . x - c (one function, unit n) takes the same
+steps: its bounds on a box are the smallest and largest values at the
+corners, it is strictly monotone along every axis with n_k != 0, the height
+criterion |d psi / d x_k| / |grad psi| is |n_k|, the root along a line is
+(c - sum over the other axes of n_a x_a) / n_k, and an interface point has
+weight w' / |n_k| and normal n.
 """
 from __future__ import annotations
 
@@ -41,11 +48,13 @@ import math
 import numpy as np
 
 from .basis import gauss_legendre
+from .geometry import Plane
 
 
 class SayeQuadrature:
     def __init__(self, balls, dim: int, q: int, max_depth: int = 4):
         self.balls = balls
+        self.plane = isinstance(balls, Plane)
         self.dim = dim
         self.q = q
         self.max_depth = max_depth
@@ -59,6 +68,18 @@ class SayeQuadrature:
 
     def _bounds(self, f, lo, hi, free):
         i, vals = f
+        if self.plane:
+            nv = self.balls.n
+            mn = 0.0
+            mx = 0.0
+            for a in range(self.dim):
+                if a in free:
+                    mn += nv[a] * lo[a] if nv[a] > 0 else nv[a] * hi[a]
+                    mx += nv[a] * hi[a] if nv[a] > 0 else nv[a] * lo[a]
+                else:
+                    mn += nv[a] * vals[a]
+                    mx += nv[a] * vals[a]
+            return mn - self.balls.c0, mx - self.balls.c0
         c = self.balls.c[i]
         near2 = 0.0
         far2 = 0.0
@@ -76,6 +97,12 @@ class SayeQuadrature:
 
     def _psi(self, f, x, free):
         i, vals = f
+        if self.plane:
+            nv = self.balls.n
+            s = 0.0
+            for a in range(self.dim):
+                s += nv[a] * self._coord(f, x, free, a)
+            return s - self.balls.c0
         c = self.balls.c[i]
         s = 0.0
         for a in range(self.dim):
@@ -84,6 +111,8 @@ class SayeQuadrature:
         return math.sqrt(s) - self.balls.r[i]
 
     def _monotone(self, f, k, lo, hi):
+        if self.plane:
+            return self.balls.n[k] != 0.0
         ck = self.balls.c[f[0]][k]
         return ck < lo[k] or ck > hi[k]
 
@@ -95,6 +124,9 @@ class SayeQuadrature:
             val = 0.0
             for f in funcs:
                 i, vals = f
+                if self.plane:
+                    val += abs(self.balls.n[k])
+                    continue
                 c = self.balls.c[i]
                 s = 0.0
                 for a in range(self.dim):
@@ -112,6 +144,18 @@ class SayeQuadrature:
         out = []
         for fi, f in enumerate(funcs):
             i, vals = f
+            if self.plane:
+                nv = self.balls.n
+                if nv[k] == 0.0:
+                    continue
+                s = 0.0
+                for ax in range(self.dim):
+                    if ax != k:
+                        s += nv[ax] * self._coord(f, x, free, ax)
+                t = (self.balls.c0 - s) / nv[k]
+                if a < t < b:
+                    out.append((t, fi))
+                continue
             c = self.balls.c[i]
             s = 0.0
             for ax in range(self.dim):
@@ -295,6 +339,11 @@ class SayeQuadrature:
                     active = False
                     break
             if not active:
+                continue
+            if self.plane:
+                sp.append(y)
+                sw.append(w / abs(self.balls.n[k]))
+                sn.append(self.balls.n.copy())
                 continue
             i = rel[fi][0]
             c = self.balls.c[i]

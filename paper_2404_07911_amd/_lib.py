@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libufem.so")
 UFEM_OK, UFEM_EINVAL, UFEM_ENOMEM, UFEM_EHIP, UFEM_EUNSUPPORTED, UFEM_ESTATE = 0, -1, -2, -3, -4, -5
 TERM_VOLUME, TERM_SIPG, TERM_NITSCHE, TERM_GHOST, TERM_ALL = 1, 2, 4, 8, 15
 F64, F32 = 0, 1
+LEVELSET_BALLS, LEVELSET_PLANE = 0, 1
 PART_INSIDE, PART_CUT_STRUCTURED, PART_CUT_LINES, PART_CUT_FACE_LINES = 1, 2, 4, 8
 PART_CUT, PART_ALL = 14, 15
 
@@ -31,6 +32,9 @@ class ufem_problem(C.Structure):
         ("gp_gamma", C.c_double),
         ("gp_jmin", C.c_int32),
         ("gp_flat", C.c_int32),
+        ("levelset", C.c_int32),
+        ("plane_normal", C.c_double * 3),
+        ("plane_offset", C.c_double),
     ]
 
 
@@ -77,6 +81,7 @@ _SIGS = {
     "ufem_destroy": (C.c_int, [_vp]),
     "ufem_info_op": (C.c_int, [_vp, C.POINTER(ufem_info)]),
     "ufem_set_terms": (C.c_int, [_vp, C.c_int32]),
+    "ufem_set_max_blocks": (C.c_int, [_vp, C.c_int32]),
     "ufem_set_kappa": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
     "ufem_apply": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "ufem_apply_part": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]),

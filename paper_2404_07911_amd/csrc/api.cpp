@@ -128,6 +128,7 @@ struct ufem_op {
   ufem::Plan P;  // host copy (layout, counts)
   int device = 0;
   int32_t terms = UFEM_TERM_ALL;
+  int32_t max_blocks = 0;
   std::vector<void*> allocs;
   int64_t bytes = 0;
   int64_t max_bytes = 0;
@@ -245,6 +246,7 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.gamma = (T)P.gamma;
   a.terms = terms;
   a.parts = 15;
+  a.max_blocks = max_blocks;
   return a;
 }
 
@@ -304,6 +306,7 @@ int ufem_plan_faces(const ufem_plan* plan, int32_t* faces) {
 
 int ufem_plan_qp(const ufem_plan* plan, double* xyz, double* ref, double* w, double* nrm) {
   if (!plan) return fail(UFEM_EINVAL, "ufem_plan_qp: null plan");
+  try {
   const ufem::Plan& P = plan->P;
   const int dim = P.dim, K = P.k;
   std::vector<double> gx, gw;
@@ -368,6 +371,11 @@ int ufem_plan_qp(const ufem_plan* plan, double* xyz, double* ref, double* w, dou
       put(q, lo, &P.surf_x[j * dim], P.surf_w[j], &P.surf_n[j * dim]);
   }
   return UFEM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(UFEM_ENOMEM, "ufem_plan_qp: host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(UFEM_EINVAL, std::string("ufem_plan_qp: ") + e.what());
+  }
 }
 
 int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_device_bytes, ufem_op** out) {
@@ -589,6 +597,12 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
   } catch (const std::bad_alloc&) {
     delete op;
     return fail(UFEM_ENOMEM, "ufem_setup: host allocation failed");
+  } catch (const std::exception& ex) {
+    delete op;
+    return fail(UFEM_EINVAL, std::string("ufem_setup: ") + ex.what());
+  } catch (...) {
+    delete op;
+    return fail(UFEM_EINVAL, "ufem_setup: unexpected host error");
   }
 }
 
@@ -600,6 +614,13 @@ int ufem_destroy(ufem_op* op) {
 int ufem_info_op(const ufem_op* op, ufem_info* info) {
   if (!op || !info) return fail(UFEM_EINVAL, "ufem_info_op: null argument");
   fill_info(op->P, info);
+  return UFEM_OK;
+}
+
+int ufem_set_max_blocks(ufem_op* op, int32_t max_blocks) {
+  if (!op) return fail(UFEM_EINVAL, "ufem_set_max_blocks: null op");
+  if (max_blocks < 0) return fail(UFEM_EINVAL, "ufem_set_max_blocks: max_blocks < 0");
+  op->max_blocks = max_blocks;
   return UFEM_OK;
 }
 

@@ -117,6 +117,9 @@ struct DevArgs {
   int32_t parts;             // stage bits: 1 inside cells, 2 structured faces and ghost
                              // penalty of the cut cells, 4 cut volume and interface
                              // lines, 8 cut-face lines
+  int32_t max_blocks;        // > 0: cap on the workgroups of every launch (the
+                             // grid-stride and persistent loops then take
+                             // several cell groups / batches per workgroup)
 };
 
 // Launchers: the per-dimension operator kernels live in op_<prec>_<dim>d.hip,
@@ -131,6 +134,7 @@ hipError_t launch_operator(const DevArgs<T>& a, int dim, int degree, const T* u,
 
 hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const void* ap, double* scal,
                            hipStream_t s);
+
 hipError_t launch_dot(int prec, int64_t n, const void* x, const void* y, double* out, hipStream_t s);
 hipError_t launch_axpby(int prec, int64_t n, double a, const void* x, double b, void* y, hipStream_t s);
 hipError_t launch_cast(int pin, int pout, int64_t n, const void* x, void* y, hipStream_t s);

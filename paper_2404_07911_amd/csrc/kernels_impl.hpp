@@ -1617,6 +1617,7 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
   const int c = lane / NL, l = lane % NL;
   const bool active = c < C;
   const int cc = active ? c : 0;
+  const bool vol_on = (a.terms & 1) != 0;  // the term mask: switched-off terms give 0
   for (int c0 = xcd_block() * C; c0 < a.n_inside; c0 += gridDim.x * C) {
     const int ci = c0 + c;
     const bool valid = active && ci < a.n_inside;
@@ -1679,7 +1680,7 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           const T wq = a.hs * Wt[qx] * Wt[qy] * Wt[q];
-          out[bz + q * K * K] = wq * (g[0][0][q] * g[1][0][q] + g[0][1][q] * g[1][1][q] + g[0][2][q] * g[1][2][q]);
+          out[bz + q * K * K] = vol_on ? wq * (g[0][0][q] * g[1][0][q] + g[0][1][q] * g[1][1][q] + g[0][2][q] * g[1][2][q]) : T(0);
         }
       }
     } else {
@@ -1697,7 +1698,7 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           const T wq = a.hs * Wt[qx] * Wt[q];
-          out[by + q * K] = wq * (g[0][0][q] * g[1][0][q] + g[0][1][q] * g[1][1][q]);
+          out[by + q * K] = vol_on ? wq * (g[0][0][q] * g[1][0][q] + g[0][1][q] * g[1][1][q]) : T(0);
         }
       }
     }
@@ -1772,7 +1773,8 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
         g[k2] = s2;
       }
       const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
-      dk[a.seg[2] + (int64_t)fi * NF + f] = wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]);
+      dk[a.seg[2] + (int64_t)fi * NF + f] =
+          (a.terms & 2) ? wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]) : T(0);
     }
     sync();
   }
@@ -1816,6 +1818,8 @@ __device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int i
     pw = a.vol_w;
     kbase = a.seg[1];
   }
+  // the term mask: points of a switched-off term get 0
+  const bool on = (a.terms & (FACE ? 2 : (kind == 1 ? 4 : 1))) != 0;
   auto coord = [&](int64_t q, int ax) -> T {
     if (FACE) {
       const int fa = ax < nax ? ax : ax - 1;
@@ -1897,7 +1901,7 @@ __device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int i
     } else {
       val = ew[1] * eu[1] + ew[2] * eu[2] + ew[3] * eu[3];
     }
-    dk[kbase + q] = c * val;
+    dk[kbase + q] = on ? c * val : T(0);
   }
 }
 
@@ -2070,7 +2074,7 @@ cut_face_dk_kernel(DevArgs<T> a, const T* __restrict__ w,
         // the lower cell: jump = own - neighbour, average of the d_n
         const T Jw = ev[0] - ev[2], Aw = T(0.5) * (ev[1] + ev[3]);
         const T Ju = ev[4] - ev[6], Au = T(0.5) * (ev[5] + ev[7]);
-        dk[a.seg[3] + q] = a.hs * a.fcut_w[q] * (-Aw * Ju - Jw * Au + a.gamma * Jw * Ju);
+        dk[a.seg[3] + q] = (a.terms & 2) ? a.hs * a.fcut_w[q] * (-Aw * Ju - Jw * Au + a.gamma * Jw * Ju) : T(0);
       }
     }
     sync();
@@ -2085,6 +2089,14 @@ int blocks_per_cu(Kern kernel) {
   return nb;
 }
 
+// workgroups of a launch: g, capped by DevArgs::max_blocks when that is set
+template <typename T>
+inline int grid_cap(const DevArgs<T>& a, int64_t g) {
+  int64_t c = std::min<int64_t>(g, 1 << 20);
+  if (a.max_blocks > 0) c = std::min<int64_t>(c, a.max_blocks);
+  return (int)c;
+}
+
 template <int K, int D, typename T>
 hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, bool adj, hipStream_t s) {
   if (adj) {
@@ -2097,32 +2109,30 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     {
       constexpr int CW = KronShape<K, D>::C, CF = FaceDkShape<K, D>::C;
       if (a.n_inside > 0)
-        inside_dk_kernel<K, D, T><<<(int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20), 64, 0, s>>>(a, x, y, dk);
+        inside_dk_kernel<K, D, T><<<grid_cap(a, (a.n_inside + CW - 1) / CW), 64, 0, s>>>(a, x, y, dk);
       if (a.n_sfaces > 0)
-        face_dk_kernel<K, D, T><<<(int)std::min<int64_t>((a.n_sfaces + CF - 1) / CF, 1 << 20), 64, 0, s>>>(a, x, y, dk);
+        face_dk_kernel<K, D, T><<<grid_cap(a, (a.n_sfaces + CF - 1) / CF), 64, 0, s>>>(a, x, y, dk);
       if (a.n_vbatch > 0)
-        cut_dk_kernel<K, D, T, false><<<std::min(a.n_vbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.vbrec, a.vdesc,
-                                                                                   a.n_vbatch);
+        cut_dk_kernel<K, D, T, false><<<grid_cap(a, a.n_vbatch), 64, 0, s>>>(a, x, y, dk, a.vbrec, a.vdesc,
+                                                                              a.n_vbatch);
       if (a.n_fbatch > 0)
-        cut_face_dk_kernel<K, D, T><<<std::min(a.n_fbatch, 1 << 20), 64, 0, s>>>(a, x, y, dk, a.fbrec, a.fdesc,
-                                                                                 a.n_fbatch);
+        cut_face_dk_kernel<K, D, T><<<grid_cap(a, a.n_fbatch), 64, 0, s>>>(a, x, y, dk, a.fbrec, a.fdesc,
+                                                                            a.n_fbatch);
     }
     return hipGetLastError();
   }
   const bool both = a.kappa == nullptr && (a.parts & 3) == 3;
+  constexpr int CW = KronShape<K, D>::C;
   if (both) {
     // inside cells and the structured faces of the cut cells in one launch
-    constexpr int CW = KronShape<K, D>::C;
     const int64_t n_all = a.n_inside + a.n_cut;
-    const int gk = (int)std::min<int64_t>((n_all + CW - 1) / CW, 1 << 20);
+    const int gk = grid_cap(a, (n_all + CW - 1) / CW);
     if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_all, (int)n_all, 1);
   } else if (a.kappa == nullptr) {
-    constexpr int CW = KronShape<K, D>::C;
-    const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
+    const int gk = (a.parts & 1) ? grid_cap(a, (a.n_inside + CW - 1) / CW) : 0;
     if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
   } else {
-    constexpr int CW = KronShape<K, D>::C;
-    const int gk = (a.parts & 1) ? (int)std::min<int64_t>((a.n_inside + CW - 1) / CW, 1 << 20) : 0;
+    const int gk = (a.parts & 1) ? grid_cap(a, (a.n_inside + CW - 1) / CW) : 0;
     if (gk > 0)
       kappa_struct_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.kface_inside,
                                                                       a.n_inside, 1);
@@ -2132,8 +2142,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     // their rows: Kronecker kernel with kappa = 1, per-point face
     // quadrature with kappa), then the volume / interface lines and the
     // cut-face lines are added
-    constexpr int CW = KronShape<K, D>::C;
-    const int gs = (a.parts & 2) && !both ? (int)std::min<int64_t>((a.n_cut + CW - 1) / CW, 1 << 20) : 0;
+    const int gs = (a.parts & 2) && !both ? grid_cap(a, (a.n_cut + CW - 1) / CW) : 0;
     if (gs > 0) {
       if (a.kappa == nullptr)
         inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
@@ -2143,12 +2152,12 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     }
     if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
       static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
-      const int g = std::min(a.n_vbatch, nb * a.n_cu);
+      const int g = grid_cap(a, std::min(a.n_vbatch, nb * a.n_cu));
       cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);
     }
     if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0) {
       static const int nb = blocks_per_cu(cut_face_kernel<K, D, T>);
-      const int g = std::min(a.n_fbatch, nb * a.n_cu);
+      const int g = grid_cap(a, std::min(a.n_fbatch, nb * a.n_cu));
       cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
     }
   }

@@ -17,12 +17,22 @@
 //  SPLIT problem (integrate over the whole box): drop functions of one sign;
 //  with none left or in 1D, Gauss rules on the pieces between roots;
 //  otherwise the same recursion with every piece kept.
+//  A plane psi = n . x - c (unit n, one function) takes the same steps: its
+//  bounds on a box are its values at the extreme corners, it is strictly
+//  monotone along every axis with n_k != 0, the height criterion is |n_k|,
+//  the root along a line is (c - sum_{a != k} n_a x_a) / n_k, and an
+//  interface point has weight w' / |n_k| and normal n.
 #include "plan.hpp"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <thread>
+
+// Every product and sum is rounded on its own (no fused multiply-add), so
+// that the decisions on signs (classes, pieces, active roots) follow the
+// plain arithmetic of the method.
+#pragma clang fp contract(off)
 
 namespace ufem {
 
@@ -161,7 +171,9 @@ struct Rule {
 
 class Saye {
  public:
-  Saye(const Plan& P) : dim_(P.dim), q_(P.q), maxd_(P.max_depth), c_(P.centers), r_(P.radii) {
+  Saye(const Plan& P)
+      : dim_(P.dim), q_(P.q), maxd_(P.max_depth), c_(P.centers), r_(P.radii), plane_(P.plane), pc_(P.pc) {
+    for (int a = 0; a < 3; ++a) pn_[a] = P.pn[a];
     gauss_legendre01(q_, gx_, gw_);
   }
   int64_t n_fallback = 0;
@@ -171,7 +183,7 @@ class Saye {
     double L[3] = {0, 0, 0}, H[3] = {0, 0, 0}, base[3] = {0, 0, 0};
     for (int a = 0; a < dim_; ++a) { L[a] = lo[a]; H[a] = hi[a]; base[a] = lo[a]; }
     std::vector<Fn> fs;
-    for (int i = 0; i < (int)r_.size(); ++i) {
+    for (int i = 0; i < nfun(); ++i) {
       Fn f;
       f.ball = i;
       for (int a = 0; a < 3; ++a) f.vals[a] = base[a];
@@ -187,7 +199,7 @@ class Saye {
     L[axis] = value;
     H[axis] = value;
     std::vector<Fn> fs;
-    for (int i = 0; i < (int)r_.size(); ++i) {
+    for (int i = 0; i < nfun(); ++i) {
       Fn f;
       f.ball = i;
       for (int a = 0; a < 3; ++a) f.vals[a] = base[a];
@@ -201,12 +213,30 @@ class Saye {
   int dim_, q_, maxd_;
   const std::vector<double>& c_;
   const std::vector<double>& r_;
+  bool plane_;
+  double pn_[3], pc_;
   std::vector<double> gx_, gw_;
 
+  int nfun() const { return plane_ ? 1 : (int)r_.size(); }
   const double* cen(int i) const { return &c_[(size_t)i * dim_]; }
   static bool isfree(int free, int a) { return (free >> a) & 1; }
 
   void bounds(const Fn& f, const double* lo, const double* hi, int free, double& mn, double& mx) const {
+    if (plane_) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int a = 0; a < dim_; ++a) {
+        if (isfree(free, a)) {
+          s0 += pn_[a] > 0 ? pn_[a] * lo[a] : pn_[a] * hi[a];
+          s1 += pn_[a] > 0 ? pn_[a] * hi[a] : pn_[a] * lo[a];
+        } else {
+          s0 += pn_[a] * f.vals[a];
+          s1 += pn_[a] * f.vals[a];
+        }
+      }
+      mn = s0 - pc_;
+      mx = s1 - pc_;
+      return;
+    }
     const double* c = cen(f.ball);
     double near2 = 0.0, far2 = 0.0;
     for (int a = 0; a < dim_; ++a) {
@@ -226,6 +256,11 @@ class Saye {
   }
   double coord(const Fn& f, const double* x, int free, int a) const { return isfree(free, a) ? x[a] : f.vals[a]; }
   double psi(const Fn& f, const double* x, int free) const {
+    if (plane_) {
+      double s = 0.0;
+      for (int a = 0; a < dim_; ++a) s += pn_[a] * coord(f, x, free, a);
+      return s - pc_;
+    }
     const double* c = cen(f.ball);
     double s = 0.0;
     for (int a = 0; a < dim_; ++a) {
@@ -235,6 +270,7 @@ class Saye {
     return std::sqrt(s) - r_[f.ball];
   }
   bool monotone(const Fn& f, int k, const double* lo, const double* hi) const {
+    if (plane_) return pn_[k] != 0.0;
     double ck = cen(f.ball)[k];
     return ck < lo[k] || ck > hi[k];
   }
@@ -249,6 +285,10 @@ class Saye {
       if (!ok) continue;
       double val = 0.0;
       for (const Fn& f : fs) {
+        if (plane_) {
+          val += std::fabs(pn_[k]);
+          continue;
+        }
         const double* c = cen(f.ball);
         double s = 0.0;
         for (int a = 0; a < dim_; ++a) {
@@ -268,6 +308,15 @@ class Saye {
     out.clear();
     for (int fi = 0; fi < (int)fs.size(); ++fi) {
       const Fn& f = fs[fi];
+      if (plane_) {
+        if (pn_[k] == 0.0) continue;
+        double s = 0.0;
+        for (int ax = 0; ax < dim_; ++ax)
+          if (ax != k) s += pn_[ax] * coord(f, x, free, ax);
+        const double t = (pc_ - s) / pn_[k];
+        if (a < t && t < b) out.push_back({t, fi});
+        continue;
+      }
       const double* c = cen(f.ball);
       double s = 0.0;
       for (int ax = 0; ax < dim_; ++ax) {
@@ -429,6 +478,12 @@ class Saye {
       for (int gi = 0; gi < (int)rel.size(); ++gi)
         if (gi != rt.fi && psi(rel[gi], y, free) < 0.0) { active = false; break; }
       if (!active) continue;
+      if (plane_) {
+        out.sx.insert(out.sx.end(), y, y + 3);
+        out.sw.push_back(w / std::fabs(pn_[k]));
+        for (int ax = 0; ax < 3; ++ax) out.sn.push_back(ax < dim_ ? pn_[ax] : 0.0);
+        continue;
+      }
       const Fn& f = rel[rt.fi];
       const double* c = cen(f.ball);
       double d[3] = {0, 0, 0}, s = 0.0;
@@ -494,6 +549,16 @@ class Saye {
 };
 
 int box_class(const Plan& P, const double* lo, const double* hi) {
+  if (P.plane) {
+    double mn = 0.0, mx = 0.0;
+    for (int a = 0; a < P.dim; ++a) {
+      mn += P.pn[a] > 0 ? P.pn[a] * lo[a] : P.pn[a] * hi[a];
+      mx += P.pn[a] > 0 ? P.pn[a] * hi[a] : P.pn[a] * lo[a];
+    }
+    mn -= P.pc;
+    mx -= P.pc;
+    return mx < 0.0 ? kInside : (mn < 0.0 ? kCut : kOutside);
+  }
   bool touch = false;
   for (size_t i = 0; i < P.radii.size(); ++i) {
     const double* c = &P.centers[i * P.dim];
@@ -561,7 +626,9 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
   if (pr.n < 2 || pr.n > 4096) return "n must be in [2, 4096]";
   if (!(pr.hi > pr.lo)) return "hi must exceed lo";
   if (pr.degree < 1 || pr.degree > 7) return "degree must be in [1, 7]";
-  if (pr.n_balls < 1 || !pr.centers || !pr.radii) return "need at least one ball (centers, radii)";
+  if (pr.levelset != UFEM_LEVELSET_BALLS && pr.levelset != UFEM_LEVELSET_PLANE) return "unknown level-set kind";
+  if (pr.levelset == UFEM_LEVELSET_BALLS && (pr.n_balls < 1 || !pr.centers || !pr.radii))
+    return "need at least one ball (centers, radii)";
   if (pr.q_cut < 0 || pr.q_cut > 16) return "q_cut must be in [0, 16]";
   if (pr.gp_jmin < 0 || pr.gp_jmin > pr.degree + 1) return "gp_jmin out of range";
   double cells = std::pow((double)pr.n, pr.dim);
@@ -575,10 +642,23 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
   P.max_depth = pr.max_depth < 0 ? 4 : pr.max_depth;
   P.lo = pr.lo;
   P.h = (pr.hi - pr.lo) / pr.n;
-  P.centers.assign(pr.centers, pr.centers + (size_t)pr.n_balls * pr.dim);
-  P.radii.assign(pr.radii, pr.radii + pr.n_balls);
-  for (double r : P.radii)
-    if (!(r > 0.0)) return "radii must be positive";
+  P.plane = pr.levelset == UFEM_LEVELSET_PLANE;
+  P.centers.clear();
+  P.radii.clear();
+  if (P.plane) {
+    double s = 0.0;
+    for (int a = 0; a < pr.dim; ++a) s += pr.plane_normal[a] * pr.plane_normal[a];
+    const double L = std::sqrt(s);
+    if (!(L > 0.0) || !std::isfinite(L) || !std::isfinite(pr.plane_offset)) return "plane normal must be nonzero and finite";
+    for (int a = 0; a < 3; ++a) P.pn[a] = a < pr.dim ? pr.plane_normal[a] / L : 0.0;
+    P.pc = pr.plane_offset / L;
+    P.prob.n_balls = 0;
+  } else {
+    P.centers.assign(pr.centers, pr.centers + (size_t)pr.n_balls * pr.dim);
+    P.radii.assign(pr.radii, pr.radii + pr.n_balls);
+    for (double r : P.radii)
+      if (!(r > 0.0)) return "radii must be positive";
+  }
   P.prob.centers = nullptr;
   P.prob.radii = nullptr;
   P.tau = pr.nitsche_factor * P.p * P.p;

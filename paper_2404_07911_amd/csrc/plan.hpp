@@ -26,6 +26,8 @@ struct Face {
 struct Plan {
   ufem_problem prob{};
   std::vector<double> centers, radii;
+  bool plane = false;              // level set n . x - c (unit n) instead of balls
+  double pn[3] = {0, 0, 0}, pc = 0.0;
   int dim = 3, n = 0, p = 1, k = 2, q = 2, max_depth = 4;
   double h = 0.0, lo = 0.0;
   double tau = 0.0, gamma = 0.0;

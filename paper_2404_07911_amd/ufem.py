@@ -15,7 +15,8 @@ from . import _lib as L
 
 @dataclasses.dataclass
 class Problem:
-    """Unfitted SIPG Poisson problem on [lo, hi]^dim cut by a union of balls
+    """Unfitted SIPG Poisson problem on [lo, hi]^dim cut by a union of balls,
+    or with ``plane = (normal, offset)`` by the half space n . x < offset
     (Sections 2.1-2.2 of the paper; face ghost penalty on cut-cell faces)."""
 
     dim: int
@@ -32,9 +33,11 @@ class Problem:
     gp_gamma: float = 0.1
     gp_jmin: int = 0
     gp_flat: bool = False
+    plane: tuple | None = None
 
     @classmethod
     def from_workload(cls, wl, **kw):
+        kw.setdefault("plane", getattr(wl, "plane", None))
         return cls(wl.dim, wl.n, wl.degree, np.asarray(wl.centers), np.asarray(wl.radii), wl.lo, wl.hi, **kw)
 
     def _struct(self):
@@ -56,6 +59,12 @@ class Problem:
         s.gp_gamma = self.gp_gamma
         s.gp_jmin = self.gp_jmin
         s.gp_flat = int(bool(self.gp_flat))
+        if self.plane is not None:
+            nrm = np.asarray(self.plane[0], dtype=np.float64).reshape(-1)
+            s.levelset = L.LEVELSET_PLANE
+            for a in range(min(3, nrm.size)):
+                s.plane_normal[a] = float(nrm[a])
+            s.plane_offset = float(self.plane[1])
         return s, (c, r)
 
 
@@ -148,6 +157,8 @@ class Operator:
         self.n_dofs = self.info["n_dofs"]
         self.n_qp = self.info["n_qp"]
         self._kappa = {L.F64: None, L.F32: None}
+        self._kappa_src = None
+        self.terms = L.TERM_ALL
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -169,6 +180,11 @@ class Operator:
 
     def set_terms(self, mask: int):
         L.check(L.lib().ufem_set_terms(self._h, int(mask)))
+        self.terms = int(mask)
+
+    def set_max_blocks(self, max_blocks: int):
+        """Cap the workgroups of every launch (0: sized by the work)."""
+        L.check(L.lib().ufem_set_max_blocks(self._h, int(max_blocks)))
 
     def set_kappa(self, kappa, stream=None):
         """kappa: device tensor of n_qp entries (float64 and/or float32) or None."""
@@ -176,6 +192,7 @@ class Operator:
             for p in (L.F64, L.F32):
                 L.check(L.lib().ufem_set_kappa(self._h, p, None, None))
                 self._kappa[p] = None
+            self._kappa_src = None
             return
         torch = _torch()
         self._check_vec(kappa, self.n_qp, "kappa")
@@ -185,6 +202,7 @@ class Operator:
         L.check(L.lib().ufem_set_kappa(self._h, L.F64, C.c_void_p(k64.data_ptr()), s))
         L.check(L.lib().ufem_set_kappa(self._h, L.F32, C.c_void_p(k32.data_ptr()), s))
         self._kappa = {L.F64: k64, L.F32: k32}
+        self._kappa_src = kappa
 
     def apply(self, u, v=None, stream=None):
         torch = _torch()
@@ -218,11 +236,16 @@ class Operator:
             raise TypeError("w and u must share a dtype")
         if atw is None:
             atw = torch.empty_like(w)
+        self._check_vec(atw, self.n_dofs, "atw")
+        if atw.dtype != w.dtype:
+            raise TypeError("atw must have the dtype of w")
         if want_dkappa and dkappa is None:
             dkappa = torch.empty(self.n_qp, dtype=w.dtype, device=w.device)
         dk_ptr = C.c_void_p(dkappa.data_ptr()) if dkappa is not None else None
         if dkappa is not None:
             self._check_vec(dkappa, self.n_qp, "dkappa")
+            if dkappa.dtype != w.dtype:
+                raise TypeError("dkappa must have the dtype of w")
         L.check(L.lib().ufem_apply_adjoint(self._h, _prec_of(w), C.c_void_p(w.data_ptr()),
                                            C.c_void_p(u.data_ptr()), C.c_void_p(atw.data_ptr()), dk_ptr,
                                            _stream_handle(stream)))
@@ -238,17 +261,30 @@ def _make_apply_fn():
 
         @staticmethod
         def forward(ctx, u, kappa, op):
-            op.set_kappa(kappa.detach() if kappa is not None else None)
-            v = op.apply(u.detach().contiguous())
+            kap = kappa.detach().contiguous() if kappa is not None else None
+            op.set_kappa(kap)
+            u_in = u.detach().contiguous()
+            v = op.apply(u_in)
+            # the operator holds one coefficient and one term mask: backward
+            # restores the ones of this forward
             ctx.op = op
-            ctx.save_for_backward(u.detach())
-            ctx.has_kappa = kappa is not None
+            ctx.terms = op.terms
+            ctx.has_kappa = kap is not None
+            ctx.save_for_backward(u_in, kap if kap is not None else u_in.new_empty(0))
             return v
 
         @staticmethod
         def backward(ctx, grad_v):
-            (u,) = ctx.saved_tensors
-            atw, dk = ctx.op.apply_adjoint(grad_v.contiguous(), u, want_dkappa=ctx.has_kappa)
+            u, kap = ctx.saved_tensors
+            op = ctx.op
+            prev_kappa, prev_terms = op._kappa_src, op.terms
+            op.set_kappa(kap if ctx.has_kappa else None)
+            op.set_terms(ctx.terms)
+            try:
+                atw, dk = op.apply_adjoint(grad_v.contiguous(), u, want_dkappa=ctx.has_kappa)
+            finally:
+                op.set_kappa(prev_kappa)
+                op.set_terms(prev_terms)
             return atw, (dk if ctx.has_kappa else None), None
 
     return UfemApply

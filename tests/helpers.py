@@ -8,7 +8,7 @@ from oracle.operator import UnfittedDG
 
 
 def oracle_for(wl, **kw):
-    return UnfittedDG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi, **kw)
+    return UnfittedDG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi, plane=wl.plane, **kw)
 
 
 def oracle_qp_arrays(op):
@@ -55,9 +55,39 @@ SMALL_CASES = {
     "ball3d_p6": (ui.ball3d, dict(seed=6, n=5, degree=6)),
     "ball3d_p7": (ui.ball3d, dict(seed=7, n=5, degree=7)),
     "disk2d_p7": (ui.disk2d, dict(seed=7, n=8, degree=7)),
+    # two balls whose intersection curve has both centres on opposite sides
+    # along every axis: no height direction exists near it, and with no
+    # subdivision allowed the cells there take the tensor rule filtered by
+    # phi < 0 (the fallback of the dimension-reduction rule)
+    "union2d_fallback": (ui.custom, dict(dim=2, n=12, degree=3, centers=[[-0.31, -0.29], [0.3, 0.32]],
+                                         radii=[0.5, 0.5], seed=21)),
+    "union3d_fallback": (ui.custom, dict(dim=3, n=8, degree=2,
+                                         centers=[[-0.31, -0.29, -0.3], [0.3, 0.32, 0.29]],
+                                         radii=[0.55, 0.55], seed=22)),
+    # degenerate cuts: a sphere centred on a mesh vertex whose radius is a
+    # multiple of h touches six mesh planes at single points and passes
+    # through mesh vertices (tangent faces carry no SIPG term, and the cells
+    # beyond them are outside)
+    "tangent3d": (ui.custom, dict(dim=3, n=8, degree=2, centers=[[0.0, 0.0, 0.0]], radii=[0.5], seed=23)),
+    "tangent2d": (ui.custom, dict(dim=2, n=8, degree=3, centers=[[0.0, 0.0]], radii=[0.5], seed=24)),
+    # plane level sets (the plane benchmark's geometry): a tilted plane
+    # through the box, and the benchmark's near-horizontal plane in one layer
+    "plane3d_p2": (ui.plane, dict(dim=3, n=8, degree=2, normal=[0.3, -0.5, 0.81], offset=0.07, seed=25)),
+    "plane2d_p3": (ui.plane, dict(dim=2, n=10, degree=3, normal=[0.6, -0.8], offset=0.05, seed=26)),
+    "plane3d_layer_p1": (ui.plane3d, dict(layer=3, n=12, degree=1, seed=27)),
+}
+
+# options of the plan and of the oracle beyond the workload (same keywords)
+CASE_OPTIONS = {
+    "union2d_fallback": dict(max_depth=0),
+    "union3d_fallback": dict(max_depth=0),
 }
 
 
 def make_case(name):
     fn, kw = SMALL_CASES[name]
     return fn(**kw)
+
+
+def case_options(name):
+    return dict(CASE_OPTIONS.get(name, {}))

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import ufem_inputs as ui
-from tests.helpers import SMALL_CASES, make_case, oracle_for, oracle_qp_arrays
+from tests.helpers import SMALL_CASES, case_options, make_case, oracle_for, oracle_qp_arrays
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -35,8 +35,9 @@ def test_plan_matches_oracle(name):
     from paper_2404_07911_amd import Plan, Problem
 
     wl, _ = make_case(name)
-    pl = Plan(Problem.from_workload(wl))
-    op = oracle_for(wl)
+    opts = case_options(name)
+    pl = Plan(Problem.from_workload(wl, **opts))
+    op = oracle_for(wl, **opts)
     assert np.array_equal(pl.cells(), op.cls)
     kinds = {"str": 0, "cut": 1, "none": 2}
     of = np.array([(a, b, c, kinds[k], int(g)) for a, b, c, k, g in op.faces], dtype=np.int32).reshape(-1, 5)
@@ -50,6 +51,31 @@ def test_plan_matches_oracle(name):
     assert np.abs(w - ow).max() < 1e-13 * max(1.0, np.abs(ow).max())
     assert np.abs(nrm - onrm).max() < 1e-13
     assert np.abs(xyz - op.qp_physical_points()).max() < 1e-13
+    assert pl.info["n_fallback"] == op.saye.n_fallback
+
+
+def test_edge_cases_reach_their_paths():
+    """The fallback cases hit the subdivision limit; in the tangent cases the
+    sphere touches mesh planes at mesh vertices only."""
+    from paper_2404_07911_amd import Plan, Problem
+
+    for name in ("union2d_fallback", "union3d_fallback"):
+        wl, _ = make_case(name)
+        pl = Plan(Problem.from_workload(wl, **case_options(name)))
+        assert pl.info["n_fallback"] > 0, name
+    for name in ("tangent2d", "tangent3d"):
+        wl, _ = make_case(name)
+        pl = Plan(Problem.from_workload(wl))
+        assert pl.info["n_fallback"] == 0
+        cls = pl.cells()
+        n = wl.n
+        # the sphere touches the plane x = 0.5 at (0.5, 0, 0), a mesh vertex:
+        # the cell beyond it is outside (distance exactly R), the one before
+        # is cut, and the pieces of zero measure are dropped (no zero weight)
+        beyond = 6 + n * (n // 2) + (n * n * (n // 2) if wl.dim == 3 else 0)
+        assert cls[beyond] == 2 and cls[beyond - 1] == 1
+        _, _, w, _ = pl.qp()
+        assert (w > 0).all()
 
 
 def test_plan_full_size_ball_counts():

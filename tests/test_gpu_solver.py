@@ -175,3 +175,49 @@ def test_dkappa_central_differences_degree4(torch):
         assert abs(fd - g) < 1e-9 * abs(g) + 8 * 2.3e-16 * L0 / h, (fd, g, L0)
     finally:
         op.set_kappa(None)
+
+
+def test_autograd_backward_uses_the_state_of_its_forward(torch, ball):
+    """Two forwards with different kappa (the second with the volume term
+    only) and a non-contiguous input, then the backward of the first: its
+    gradients are those of the first forward's operator (kappa1, every
+    term), against the oracle; the operator's state is left as it was."""
+    from oracle.operator import VOL
+
+    from paper_2404_07911_amd import TERM_ALL, TERM_VOLUME, ufem_apply
+
+    wl, ora, op, ustar = ball
+    rng = np.random.default_rng(19)
+    n = ora.n_dofs
+    bvec = rng.uniform(-1, 1, n)
+    pts = ora.qp_physical_points()
+    kap1 = ui.kappa_field(pts)
+    kap2 = 2.0 + np.cos(pts[:, 0])
+    # u as a strided view (every other entry of a longer vector)
+    base = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    base[::2] = torch.from_numpy(ustar).cuda()
+    u = base[::2].detach().requires_grad_(True)
+    assert not u.is_contiguous()
+    k1 = torch.from_numpy(kap1).cuda().requires_grad_(True)
+    k2 = torch.from_numpy(kap2).cuda().requires_grad_(True)
+    bt = torch.from_numpy(bvec).cuda()
+    try:
+        v1 = ufem_apply(u, k1, op)
+        op.set_terms(TERM_VOLUME)
+        v2 = ufem_apply(u, k2, op)
+        loss = 0.5 * ((v1 - bt) ** 2).sum()
+        loss.backward()
+        r = ora.apply(ustar, ALL, kap1) - bvec
+        gu = ora.apply(r, ALL, kap1)
+        gk = ora.dkappa(r, ustar)
+        ru = np.abs(u.grad.cpu().numpy() - gu).max() / np.abs(gu).max()
+        rk = np.abs(k1.grad.cpu().numpy() - gk).max() / np.abs(gk).max()
+        assert ru < 1e-12 and rk < 1e-12, (ru, rk)
+        assert op.terms == TERM_VOLUME
+        # the second forward's operator is still in place
+        v2b = op.apply(torch.from_numpy(ustar).cuda()).cpu().numpy()
+        assert np.abs(v2b - ora.apply(ustar, VOL, kap2)).max() < 1e-12 * np.abs(v2b).max()
+        assert np.abs(v2.detach().cpu().numpy() - v2b).max() == 0.0
+    finally:
+        op.set_terms(TERM_ALL)
+        op.set_kappa(None)

@@ -21,6 +21,12 @@ Workloads (all on the box [-1, 1]^d, uniform background mesh of n^d cells):
   coefficient kappa(x) = 1 + 0.5 sin(pi x) sin(pi y) sin(pi z).
 * ``balls3d``  -- 3D, degree 3, 128^3 cells, union of 20 balls with centres
   uniform in [-0.7, 0.7]^3 and radii uniform in [0.1, 0.3].
+* ``plane3d``  -- the plane benchmark (Section 5.2): 3D, degree 1 or 3, n^3
+  cells, domain below a plane z ~ const whose normal is tilted by (1e-3,
+  2e-3) and whose position lies in layer L of the cells (a seeded offset
+  within the middle third of the layer): layers below are inside, layer L
+  is cut, so the ratio of cut to physical cells is 1 / (L + 1); L = n puts
+  the plane above the box (no cut cell).
 
 The paper measures on spheres and random sphere unions of its own (Section 6);
 these seeded geometries stand in for them.
@@ -48,6 +54,7 @@ class Workload:
     seed: int
     lo: float = -1.0
     hi: float = 1.0
+    plane: tuple | None = None  # (normal, offset): level set n . x - offset instead of balls
 
     @property
     def h(self) -> float:
@@ -100,6 +107,30 @@ def custom(dim: int, n: int, degree: int, centers, radii, seed: int = 0, name: s
     c = np.asarray(centers, dtype=np.float64).reshape(-1, dim)
     r = np.asarray(radii, dtype=np.float64).reshape(-1)
     return Workload(name, dim, n, degree, c, r, seed), rng
+
+
+def plane(dim: int, n: int, degree: int, normal, offset, seed: int = 0, name: str = "plane"):
+    rng = make_rng(seed)
+    nv = np.asarray(normal, dtype=np.float64).reshape(-1)
+    return Workload(name, dim, n, degree, np.zeros((0, dim)), np.zeros(0), seed,
+                    plane=(nv, float(offset))), rng
+
+
+PLANE_TILT = (1e-3, 2e-3)
+
+
+def plane3d(layer: int, seed: int = 0, n: int = 128, degree: int = 1):
+    """Plane benchmark: cut-cell ratio 1 / (layer + 1) (0 for layer >= n)."""
+    rng = make_rng(seed)
+    h = 2.0 / n
+    jitter = rng.uniform(-h / 6, h / 6)
+    if layer >= n:
+        offset = 1.5
+    else:
+        offset = -1.0 + (layer + 0.5) * h + jitter
+    nv = np.array([PLANE_TILT[0], PLANE_TILT[1], 1.0])
+    wl = Workload("plane3d", 3, n, degree, np.zeros((0, 3)), np.zeros(0), seed, plane=(nv, offset))
+    return wl, rng
 
 
 def uniform_vector(rng: np.random.Generator, n: int) -> np.ndarray:
