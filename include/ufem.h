@@ -153,6 +153,29 @@ int ufem_plan_faces(const ufem_plan* plan, int32_t* faces);
  * NULL. */
 int ufem_plan_qp(const ufem_plan* plan, double* xyz, double* ref, double* w, double* nrm);
 
+/* Replace the plan's dimension-reduction rules by explicit ones: the
+ * "quadrature" input of setup, for rules from another generator (Section 2.3
+ * only requires some quadrature of the cut cells, cut faces and interface).
+ * The cells, faces and their classes stay; the counts, the point lines and
+ * the kappa layout (ufem_plan_info) are rebuilt.  Host arrays:
+ *   vol_count[n_cut], face_count[n_faces_cut], surf_count[n_cut]: points of
+ *     each cut cell's volume rule, each cut face's rule and each cut cell's
+ *     interface rule (cut cells in active order, cut faces in face order);
+ *   ref[dim * N], w[N], nrm[dim * N] with N the sum of all counts: the
+ *     points of the three rules in kappa order (every cut cell's volume
+ *     rule, then every cut face's rule, then every interface rule), as
+ *     ufem_plan_qp exports them for the segments seg[1]..seg[2],
+ *     seg[3]..seg[4] and seg[4]..seg[5]: reference coordinates in [0, 1]
+ *     (face points in the lower cell; their face-axis coordinate is not
+ *     read), reference weights >= 0, unit normals (read for interface points
+ *     only).
+ * Errors: EINVAL for a null array where points exist, a negative count,
+ * coordinates outside [0, 1] (1e-12 slack), non-finite values or negative
+ * weights (the plan is then unchanged); EUNSUPPORTED beyond 2^31 points of
+ * a kind.  Operators set up before the call keep their rules. */
+int ufem_plan_import_quadrature(ufem_plan* plan, const int64_t* vol_count, const int64_t* face_count,
+                                const int64_t* surf_count, const double* ref, const double* w, const double* nrm);
+
 /* Upload the plan to `device` and build the operator.  The plan may be
  * destroyed afterwards.  Allocates all device memory the operator needs
  * (max_device_bytes > 0 caps it; ENOMEM beyond).  Tables are stored for both

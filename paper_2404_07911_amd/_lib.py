@@ -77,6 +77,7 @@ _SIGS = {
     "ufem_plan_cells": (C.c_int, [_vp, _vp]),
     "ufem_plan_faces": (C.c_int, [_vp, _vp]),
     "ufem_plan_qp": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ufem_plan_import_quadrature": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ufem_setup": (C.c_int, [_vp, C.c_int, _vp, C.c_int64, C.POINTER(_vp)]),
     "ufem_destroy": (C.c_int, [_vp]),
     "ufem_info_op": (C.c_int, [_vp, C.POINTER(ufem_info)]),

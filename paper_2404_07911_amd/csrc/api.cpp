@@ -378,6 +378,23 @@ int ufem_plan_qp(const ufem_plan* plan, double* xyz, double* ref, double* w, dou
   }
 }
 
+int ufem_plan_import_quadrature(ufem_plan* plan, const int64_t* vol_count, const int64_t* face_count,
+                                const int64_t* surf_count, const double* ref, const double* w, const double* nrm) {
+  if (!plan) return fail(UFEM_EINVAL, "ufem_plan_import_quadrature: null plan");
+  try {
+    ufem::Plan Q = plan->P;  // the plan is left unchanged on failure
+    int code = UFEM_OK;
+    std::string msg = ufem::import_rules(Q, vol_count, face_count, surf_count, ref, w, nrm, &code);
+    if (code != UFEM_OK) return fail(code, "ufem_plan_import_quadrature: " + msg);
+    plan->P = std::move(Q);
+    return UFEM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(UFEM_ENOMEM, "ufem_plan_import_quadrature: host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(UFEM_EINVAL, std::string("ufem_plan_import_quadrature: ") + e.what());
+  }
+}
+
 int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_device_bytes, ufem_op** out) {
   (void)stream;
   if (!plan || !out) return fail(UFEM_EINVAL, "ufem_setup: null argument");

@@ -620,6 +620,75 @@ void group_lines(const std::vector<double>& x, int nc, int64_t begin, int64_t en
 
 }  // namespace
 
+// Point lines and the kappa layout from the cut rules in P (vol / surf /
+// fcut arrays with their offsets); shared by build_plan and the import of
+// explicit rules.
+std::string finish_rules(Plan& P, int* code) {
+  const int dim = P.dim;
+  const size_t ncut = P.cut.size();
+  const std::vector<int32_t>& cutfaces = P.fcut_face;
+  P.max_qp_cut_cell = 0;
+  for (size_t i = 0; i < ncut; ++i) P.max_qp_cut_cell = std::max<int64_t>(P.max_qp_cut_cell, P.vol_off[i + 1] - P.vol_off[i]);
+  // -- point lines
+  if (P.vol_w.size() > 0x7fffffffu || P.surf_w.size() > 0x7fffffffu || P.fcut_w.size() > 0x7fffffffu) {
+    *code = UFEM_EUNSUPPORTED;
+    return "too many cut quadrature points for 32-bit point indices";
+  }
+  P.line_first.clear(); P.line_n.clear(); P.line_axis.clear(); P.line_kind.clear();
+  P.cell_line_off.assign(ncut + 1, 0);
+  for (size_t i = 0; i < ncut; ++i) {
+    const size_t l0 = P.line_first.size();
+    group_lines(P.vol_x, dim, P.vol_off[i], P.vol_off[i + 1], 0, dim - 1, P);
+    // interface points: one-point lines along the cell's most frequent axis
+    int cnt[3] = {0, 0, 0};
+    for (size_t l = l0; l < P.line_first.size(); ++l) cnt[P.line_axis[l]] += P.line_n[l];
+    int dom = dim - 1;
+    for (int a = 0; a < dim; ++a)
+      if (cnt[a] > cnt[dom]) dom = a;
+    for (int64_t q = P.surf_off[i]; q < P.surf_off[i + 1]; ++q) {
+      P.line_first.push_back((int32_t)q);
+      P.line_n.push_back(1);
+      P.line_axis.push_back(dom);
+      P.line_kind.push_back(1);
+    }
+    P.cell_line_off[i + 1] = (int64_t)P.line_first.size();
+  }
+  P.face_line_off.assign(cutfaces.size() + 1, P.cell_line_off[ncut]);
+  for (size_t i = 0; i < cutfaces.size(); ++i) {
+    group_lines(P.fcut_x, dim - 1, P.fcut_off[i], P.fcut_off[i + 1], 2, 0, P);
+    P.face_line_off[i + 1] = (int64_t)P.line_first.size();
+  }
+
+  // -- kappa layout
+  const int nd = P.nd(), nf = P.nf();
+  P.seg[0] = 0;
+  P.seg[1] = (int64_t)P.inside.size() * nd;
+  P.seg[2] = P.seg[1] + P.vol_off[ncut];
+  int64_t off = P.seg[2];
+  P.n_faces_str = P.n_faces_cut = P.n_faces_gp = 0;
+  for (Face& f : P.faces) {
+    if (f.gp) ++P.n_faces_gp;
+    if (f.kind == kFaceStructured) {
+      f.qp_off = off;
+      f.qp_n = nf;
+      off += nf;
+      ++P.n_faces_str;
+    }
+  }
+  P.seg[3] = off;
+  for (size_t i = 0; i < cutfaces.size(); ++i) {
+    Face& f = P.faces[cutfaces[i]];
+    f.qp_off = off + P.fcut_off[i];
+    f.qp_n = (int32_t)(P.fcut_off[i + 1] - P.fcut_off[i]);
+    ++P.n_faces_cut;
+  }
+  off += P.fcut_off[cutfaces.size()];
+  P.seg[4] = off;
+  P.seg[5] = off + P.surf_off[ncut];
+  *code = UFEM_OK;
+  return std::string();
+}
+
 std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
   *code = UFEM_EINVAL;
   if (pr.dim != 2 && pr.dim != 3) return "dim must be 2 or 3";
@@ -802,64 +871,65 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
     P.fcut_off[i + 1] = P.fcut_off[i] + (int64_t)R.vw.size();
   }
 
-  // -- point lines
-  if (P.vol_w.size() > 0x7fffffffu || P.surf_w.size() > 0x7fffffffu || P.fcut_w.size() > 0x7fffffffu) {
+  return finish_rules(P, code);
+}
+
+std::string import_rules(Plan& P, const int64_t* vc, const int64_t* fc, const int64_t* sc, const double* ref,
+                         const double* w, const double* nrm, int* code) {
+  *code = UFEM_EINVAL;
+  const int dim = P.dim;
+  const size_t ncut = P.cut.size(), nfc = P.fcut_face.size();
+  if ((ncut && (!vc || !sc)) || (nfc && !fc)) return "point counts missing";
+  int64_t nv = 0, nf = 0, ns = 0;
+  for (size_t i = 0; i < ncut; ++i) {
+    if (vc[i] < 0 || sc[i] < 0) return "negative point count";
+    nv += vc[i];
+    ns += sc[i];
+  }
+  for (size_t i = 0; i < nfc; ++i) {
+    if (fc[i] < 0) return "negative point count";
+    nf += fc[i];
+  }
+  const int64_t total = nv + nf + ns;
+  if (nv > 0x7fffffff || nf > 0x7fffffff || ns > 0x7fffffff) {
     *code = UFEM_EUNSUPPORTED;
     return "too many cut quadrature points for 32-bit point indices";
   }
-  P.line_first.clear(); P.line_n.clear(); P.line_axis.clear(); P.line_kind.clear();
-  P.cell_line_off.assign(ncut + 1, 0);
-  for (size_t i = 0; i < ncut; ++i) {
-    const size_t l0 = P.line_first.size();
-    group_lines(P.vol_x, dim, P.vol_off[i], P.vol_off[i + 1], 0, dim - 1, P);
-    // interface points: one-point lines along the cell's most frequent axis
-    int cnt[3] = {0, 0, 0};
-    for (size_t l = l0; l < P.line_first.size(); ++l) cnt[P.line_axis[l]] += P.line_n[l];
-    int dom = dim - 1;
+  if (total > 0 && (!ref || !w || (ns > 0 && !nrm))) return "null point arrays";
+  const double tol = 1e-12;
+  for (int64_t q = 0; q < total; ++q) {
+    if (!std::isfinite(w[q]) || w[q] < 0.0) return "weights must be finite and non-negative";
+    for (int a = 0; a < dim; ++a) {
+      const double x = ref[q * dim + a];
+      if (!std::isfinite(x) || x < -tol || x > 1.0 + tol) return "reference coordinates must lie in [0, 1]";
+    }
+  }
+  for (int64_t q = nv + nf; q < total; ++q)
     for (int a = 0; a < dim; ++a)
-      if (cnt[a] > cnt[dom]) dom = a;
-    for (int64_t q = P.surf_off[i]; q < P.surf_off[i + 1]; ++q) {
-      P.line_first.push_back((int32_t)q);
-      P.line_n.push_back(1);
-      P.line_axis.push_back(dom);
-      P.line_kind.push_back(1);
-    }
-    P.cell_line_off[i + 1] = (int64_t)P.line_first.size();
+      if (!std::isfinite(nrm[q * dim + a])) return "normals must be finite";
+  P.vol_off.assign(ncut + 1, 0);
+  P.surf_off.assign(ncut + 1, 0);
+  P.fcut_off.assign(nfc + 1, 0);
+  for (size_t i = 0; i < ncut; ++i) {
+    P.vol_off[i + 1] = P.vol_off[i] + vc[i];
+    P.surf_off[i + 1] = P.surf_off[i] + sc[i];
   }
-  P.face_line_off.assign(cutfaces.size() + 1, P.cell_line_off[ncut]);
-  for (size_t i = 0; i < cutfaces.size(); ++i) {
-    group_lines(P.fcut_x, dim - 1, P.fcut_off[i], P.fcut_off[i + 1], 2, 0, P);
-    P.face_line_off[i + 1] = (int64_t)P.line_first.size();
+  for (size_t i = 0; i < nfc; ++i) P.fcut_off[i + 1] = P.fcut_off[i] + fc[i];
+  P.vol_x.assign(ref, ref + nv * dim);
+  P.vol_w.assign(w, w + nv);
+  P.fcut_x.clear();
+  P.fcut_x.reserve((size_t)nf * (dim - 1));
+  for (size_t i = 0; i < nfc; ++i) {
+    const int axis = P.faces[P.fcut_face[i]].axis;
+    for (int64_t q = nv + P.fcut_off[i]; q < nv + P.fcut_off[i + 1]; ++q)
+      for (int a = 0; a < dim; ++a)
+        if (a != axis) P.fcut_x.push_back(ref[q * dim + a]);
   }
-
-  // -- kappa layout
-  const int nd = P.nd(), nf = P.nf();
-  P.seg[0] = 0;
-  P.seg[1] = (int64_t)P.inside.size() * nd;
-  P.seg[2] = P.seg[1] + P.vol_off[ncut];
-  int64_t off = P.seg[2];
-  P.n_faces_str = P.n_faces_cut = P.n_faces_gp = 0;
-  for (Face& f : P.faces) {
-    if (f.gp) ++P.n_faces_gp;
-    if (f.kind == kFaceStructured) {
-      f.qp_off = off;
-      f.qp_n = nf;
-      off += nf;
-      ++P.n_faces_str;
-    }
-  }
-  P.seg[3] = off;
-  for (size_t i = 0; i < cutfaces.size(); ++i) {
-    Face& f = P.faces[cutfaces[i]];
-    f.qp_off = off + P.fcut_off[i];
-    f.qp_n = (int32_t)(P.fcut_off[i + 1] - P.fcut_off[i]);
-    ++P.n_faces_cut;
-  }
-  off += P.fcut_off[cutfaces.size()];
-  P.seg[4] = off;
-  P.seg[5] = off + P.surf_off[ncut];
-  *code = UFEM_OK;
-  return std::string();
+  P.fcut_w.assign(w + nv, w + nv + nf);
+  P.surf_x.assign(ref + (nv + nf) * dim, ref + total * dim);
+  P.surf_w.assign(w + nv + nf, w + total);
+  P.surf_n.assign(nrm + (nv + nf) * dim, nrm + total * dim);
+  return finish_rules(P, code);
 }
 
 }  // namespace ufem

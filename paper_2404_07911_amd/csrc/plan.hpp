@@ -75,6 +75,10 @@ struct Plan {
 
 // Builds the plan; returns an error message (empty on success).
 std::string build_plan(const ufem_problem& prob, Plan& plan, int* code);
+// Replaces the cut rules by explicit ones (layout of ufem_plan_import_quadrature)
+// and rebuilds the point lines and the kappa layout.
+std::string import_rules(Plan& plan, const int64_t* vol_count, const int64_t* face_count, const int64_t* surf_count,
+                         const double* ref, const double* w, const double* nrm, int* code);
 
 // 1D rules and Lagrange data used by the plan and the device tables.
 void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);

@@ -106,6 +106,28 @@ class Plan:
             L.check(L.lib().ufem_plan_faces(self._h, out.ctypes.data))
         return out
 
+    def import_quadrature(self, vol_count, face_count, surf_count, ref, w, nrm):
+        """Replace the cut rules (layout of ufem_plan_import_quadrature: point
+        counts per cut cell / cut face / cut cell, then reference points,
+        weights and normals of the three segments in kappa order)."""
+        d = self.problem.dim
+        vc = np.ascontiguousarray(vol_count, dtype=np.int64)
+        fc = np.ascontiguousarray(face_count, dtype=np.int64)
+        sc = np.ascontiguousarray(surf_count, dtype=np.int64)
+        if vc.size != self.info["n_cut"] or sc.size != self.info["n_cut"] or fc.size != self.info["n_faces_cut"]:
+            raise ValueError("one count per cut cell, cut face and cut cell")
+        n = int(vc.sum() + fc.sum() + sc.sum())
+        r = np.ascontiguousarray(ref, dtype=np.float64).reshape(-1)
+        wt = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        nm = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1)
+        if r.size != n * d or wt.size != n or nm.size != n * d:
+            raise ValueError(f"expected {n} points ({n * d} coordinates)")
+        L.check(L.lib().ufem_plan_import_quadrature(self._h, vc.ctypes.data, fc.ctypes.data, sc.ctypes.data,
+                                                    r.ctypes.data, wt.ctypes.data, nm.ctypes.data))
+        inf = L.ufem_info()
+        L.check(L.lib().ufem_plan_info(self._h, C.byref(inf)))
+        self.info = inf.as_dict()
+
     def qp(self):
         """Physical points, reference points, reference weights, normals of
         every quadrature point in kappa order."""

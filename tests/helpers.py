@@ -91,3 +91,17 @@ def make_case(name):
 
 def case_options(name):
     return dict(CASE_OPTIONS.get(name, {}))
+
+
+def oracle_cut_rules(op):
+    """The oracle's cut rules in the layout of ufem_plan_import_quadrature:
+    counts per cut cell (volume), cut face and cut cell (interface), then the
+    reference points, weights and normals of those three kappa segments."""
+    L = op.layout()
+    ref, w, nrm = oracle_qp_arrays(op)
+    seg = L["segments"]
+    vc = [L["vol"][b][1] for b in op.cut_cells]
+    fc = [L["face"][fi][1] for fi, f in enumerate(op.faces) if f[3] == "cut"]
+    sc = [L["surf"][b][1] for b in op.cut_cells]
+    sl = np.r_[seg[1]:seg[2], seg[3]:seg[5]]
+    return np.array(vc), np.array(fc), np.array(sc), ref[sl], w[sl], nrm[sl]

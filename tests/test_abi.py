@@ -153,3 +153,55 @@ def test_setup_without_gpu_fails_cleanly():
     rc = L.lib().ufem_setup(pl.handle, 0, None, 0, C.byref(h))
     assert rc in (L.UFEM_EHIP, L.UFEM_EINVAL)
     assert not h.value
+
+
+@pytest.mark.parametrize("name", ["ball3d_p3", "disk2d_p2", "balls3d_p2", "plane3d_p2", "union3d_fallback"])
+def test_import_quadrature_replaces_the_cut_rules(name):
+    """The oracle's rules with q = p + 2 points per 1D piece (not the plan's
+    own q = p + 1) go into the plan: its counts, kappa layout and exported
+    points are then exactly the oracle's."""
+    from paper_2404_07911_amd import Plan, Problem
+    from tests.helpers import oracle_cut_rules
+
+    wl, _ = make_case(name)
+    opts = case_options(name)
+    pl = Plan(Problem.from_workload(wl, **opts))
+    ora = oracle_for(wl, q=wl.degree + 2, **opts)
+    pl.import_quadrature(*oracle_cut_rules(ora))
+    L = ora.layout()
+    assert list(pl.info["seg"]) == list(L["segments"])
+    xyz, ref, w, nrm = pl.qp()
+    oref, ow, onrm = oracle_qp_arrays(ora)
+    seg = L["segments"]
+    cut = np.r_[seg[1]:seg[2], seg[3]:seg[5]]  # imported: bit for bit
+    face_axis = np.abs(ref[cut] - oref[cut]).max(axis=1) if cut.size else np.zeros(0)
+    assert np.array_equal(w[cut], ow[cut]) and np.array_equal(nrm[cut], onrm[cut])
+    assert (face_axis == 0).all()
+    # the tensor rules of the plan's own (structured) segments agree to rounding
+    assert np.abs(w - ow).max() < 1e-15 and np.abs(ref - oref).max() < 1e-15
+    assert pl.info["max_qp_cut_cell"] == max(L["vol"][b][1] for b in ora.cut_cells)
+
+
+def test_import_quadrature_rejects_bad_rules():
+    from paper_2404_07911_amd import Plan, Problem, UfemError
+    from tests.helpers import oracle_cut_rules
+
+    wl, _ = make_case("disk2d_p2")
+    pl = Plan(Problem.from_workload(wl))
+    before = dict(pl.info)
+    vc, fc, sc, ref, w, nrm = oracle_cut_rules(oracle_for(wl))
+    bad = [
+        (np.where(np.arange(vc.size) == 0, -1, vc), fc, sc, ref, w, nrm),
+        (vc, fc, sc, np.where(np.arange(ref.size).reshape(ref.shape) == 0, 1.5, ref), w, nrm),
+        (vc, fc, sc, ref, np.where(np.arange(w.size) == 3, -0.1, w), nrm),
+        (vc, fc, sc, ref, np.where(np.arange(w.size) == 3, np.nan, w), nrm),
+    ]
+    for args in bad:
+        with pytest.raises((UfemError, ValueError)):
+            pl.import_quadrature(*args)
+    # a null pointer through the ABI
+    L = _lib()
+    assert L.lib().ufem_plan_import_quadrature(pl.handle, None, None, None, None, None, None) == L.UFEM_EINVAL
+    inf = L.ufem_info()
+    L.check(L.lib().ufem_plan_info(pl.handle, C.byref(inf)))
+    assert inf.as_dict() == before

@@ -337,3 +337,33 @@ def test_dkappa_follows_the_term_mask(torch):
             assert np.abs(dk - ref).max() <= 1e-12 * np.abs(full).max(), mask
     finally:
         op.set_terms(TERM_ALL)
+
+
+@pytest.mark.parametrize("name", ["ball3d_p3", "disk2d_p2", "balls3d_p2", "plane3d_p2", "union3d_fallback"])
+def test_apply_with_imported_oracle_quadrature(torch, name):
+    """setup(..., quadrature): the oracle's own cut rules (q = p + 2 points
+    per 1D piece, not the plan's q = p + 1) imported into the plan; the
+    operator then equals the oracle built on the same rules, apply, FP32
+    apply and the adjoint pass with a kappa field."""
+    from paper_2404_07911_amd import Operator, Plan, Problem
+    from tests.helpers import oracle_cut_rules
+
+    wl, rng = make_case(name)
+    opts = case_options(name)
+    ora = oracle_for(wl, q=wl.degree + 2, **opts)
+    pl = Plan(Problem.from_workload(wl, **opts))
+    pl.import_quadrature(*oracle_cut_rules(ora))
+    op = Operator(pl)
+    u = ui.uniform_vector(rng, ora.n_dofs)
+    w = ui.uniform_vector(rng, ora.n_dofs)
+    ud = torch.from_numpy(u).cuda()
+    _say(f"[{name}] imported rules")
+    assert _rel(op.apply(ud).cpu().numpy(), ora.apply(u)) < TOL64
+    u32 = u.astype(np.float32)
+    v32 = op.apply(torch.from_numpy(u32).cuda()).cpu().numpy().astype(np.float64)
+    assert _rel(v32, ora.apply(u32.astype(np.float64))) < TOL32
+    kap = ui.kappa_field(ora.qp_physical_points())
+    op.set_kappa(torch.from_numpy(kap).cuda())
+    atw, dk = op.apply_adjoint(torch.from_numpy(w).cuda(), ud)
+    assert _rel(atw.cpu().numpy(), ora.apply(w, ALL, kap)) < TOL64
+    assert _rel(dk.cpu().numpy(), ora.dkappa(w, u)) < TOL64
