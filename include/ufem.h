@@ -266,6 +266,26 @@ int ufem_cast(int32_t precision_in, int32_t precision_out, int64_t n, const void
 int ufem_cg_iterate(ufem_op* op, int32_t precision, int32_t n_iter, void* x, void* r, void* p, void* ap,
                     double* scal, void* stream);
 
+/* ufem_cg_iterate without a workspace argument and without any allocation,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The CG
+ * scalars and the vector A p live in a fixed device array of the library,
+ * one per device, held until the process ends: 64 MiB for A p (n_dofs up to
+ * 8,388,608 float64 or 16,777,216 float32 values; EINVAL beyond) after 256
+ * bytes of scalars.  Its device address is taken once per device by
+ * ufem_setup.  Every call clears the scalars and computes r.r itself, so
+ * only x, r, p carry state between calls: on entry r = b - A x and p = r
+ * (or the r, p a previous call returned); on return x, r, p are advanced by
+ * n_iter iterations as by ufem_cg_iterate, result[0] = r.r of the new
+ * residual and result[1] != 0 if p.Ap <= 0 occurred (breakdown; the
+ * remaining iterations did nothing).  x, r, p: device, n_dofs values of
+ * `precision`, not overlapping; result: device, 2 float64.  All calls on
+ * one device share the array: calls that overlap in time on one device
+ * (two streams, or two host threads) race and give wrong results.
+ * Asynchronous on `stream`; allocates nothing. */
+int ufem_cg_iterate_static(ufem_op* op, int32_t precision, int32_t n_iter, void* x, void* r, void* p,
+                           double* result, void* stream);
+
 /* Thread-local message of the last failing call (never NULL). */
 const char* ufem_last_error(void);
 

@@ -88,6 +88,7 @@ _SIGS = {
     "ufem_apply_part": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]),
     "ufem_apply_adjoint": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "ufem_cg_iterate": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ufem_cg_iterate_static": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "ufem_dot": (C.c_int, [C.c_int32, C.c_int64, _vp, _vp, _vp, _vp]),
     "ufem_axpby": (C.c_int, [C.c_int32, C.c_int64, C.c_double, _vp, C.c_double, _vp, _vp]),
     "ufem_cast": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, _vp, _vp, _vp]),

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -44,6 +45,30 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+// Device address of the static CG workspace, per device (set at the first
+// ufem_setup on that device, with the device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+int init_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(UFEM_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return UFEM_OK;
+  void* p = nullptr;
+  hipError_t e = ufem::static_scratch_address(&p);
+  if (e != hipSuccess) return hipfail(e, "hipGetSymbolAddress(scratch)");
+  if (!p) return fail(UFEM_EHIP, "hipGetSymbolAddress(scratch) returned null");
+  g_scratch[device] = p;
+  return UFEM_OK;
+}
+
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
 
 void fill_info(const ufem::Plan& P, ufem_info* I) {
   std::memset(I, 0, sizeof(*I));
@@ -405,6 +430,10 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
   if (device < 0 || device >= ndev) return fail(UFEM_EINVAL, "ufem_setup: no such device");
   DeviceGuard guard(device);
   if (!guard.ok) return fail(UFEM_EHIP, "ufem_setup: hipSetDevice failed");
+  {
+    const int rc = init_static_scratch(device);
+    if (rc != UFEM_OK) return rc;
+  }
   ufem_op* op = nullptr;
   try {
     op = new ufem_op();
@@ -751,6 +780,49 @@ int ufem_cg_iterate(ufem_op* op, int32_t precision, int32_t n_iter, void* x, voi
     e = ufem::launch_cg_tail(precision, n, x, r, p, ap, scal, (hipStream_t)stream);
     if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate: vector update");
   }
+  return UFEM_OK;
+}
+
+int ufem_cg_iterate_static(ufem_op* op, int32_t precision, int32_t n_iter, void* x, void* r, void* p,
+                           double* result, void* stream) {
+  if (!op || !x || !r || !p || !result) return fail(UFEM_EINVAL, "ufem_cg_iterate_static: null argument");
+  if (n_iter < 0) return fail(UFEM_EINVAL, "ufem_cg_iterate_static: n_iter < 0");
+  if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_cg_iterate_static: bad precision");
+  const size_t s = precision == UFEM_F64 ? 8 : 4;
+  const size_t bytes = (size_t)op->P.n_dofs() * s;
+  if (bytes > ufem::kStaticScratchBytes - ufem::kStaticCgScalarBytes)
+    return fail(UFEM_EINVAL, "ufem_cg_iterate_static: n_dofs exceeds the static workspace (" +
+                                 std::to_string((ufem::kStaticScratchBytes - ufem::kStaticCgScalarBytes) / s) +
+                                 " values of this precision)");
+  const void* vec[3] = {x, r, p};
+  for (int i = 0; i < 3; ++i) {
+    for (int j = i + 1; j < 3; ++j)
+      if (overlap(vec[i], vec[j], bytes)) return fail(UFEM_EINVAL, "ufem_cg_iterate_static: vectors overlap");
+    if (overlap2(result, 2 * sizeof(double), vec[i], bytes))
+      return fail(UFEM_EINVAL, "ufem_cg_iterate_static: result overlaps a vector");
+  }
+  char* ws = (char*)static_scratch(op->device);
+  if (!ws) return fail(UFEM_ESTATE, "ufem_cg_iterate_static: no workspace address for the operator's device");
+  double* scal = (double*)ws;
+  void* ap = ws + ufem::kStaticCgScalarBytes;
+  DeviceGuard g(op->device);
+  const int64_t n = op->P.n_dofs();
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = ufem::launch_cg_static_begin(precision, n, r, scal, st);
+  if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate_static: r.r");
+  for (int it = 0; it < n_iter; ++it) {
+    if (precision == UFEM_F64)
+      e = ufem::launch_operator<double>(op->args<double>(op->prec[0]), op->P.dim, op->P.p, (const double*)p,
+                                        (double*)ap, nullptr, nullptr, false, st);
+    else
+      e = ufem::launch_operator<float>(op->args<float>(op->prec[1]), op->P.dim, op->P.p, (const float*)p,
+                                       (float*)ap, nullptr, nullptr, false, st);
+    if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate_static: apply");
+    e = ufem::launch_cg_tail(precision, n, x, r, p, ap, scal, st);
+    if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate_static: vector update");
+  }
+  e = ufem::launch_cg_static_end(scal, result, st);
+  if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate_static: result");
   return UFEM_OK;
 }
 

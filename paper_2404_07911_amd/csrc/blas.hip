@@ -105,7 +105,44 @@ __global__ void cg_roll_kernel(double* scal) {
   scal[2] = 0.0;
 }
 
+// the static-workspace CG: scalars cleared before r.r is accumulated, and
+// the result (new r.r, breakdown flag) copied out at the end
+__global__ void cg_clear4_kernel(double* scal) {
+  if (blockIdx.x == 0 && threadIdx.x < 4) scal[threadIdx.x] = 0.0;
+}
+
+__global__ void cg_result_kernel(const double* __restrict__ scal, double* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out[0] = scal[0];
+    out[1] = scal[3];
+  }
+}
+
 }  // namespace
+
+// Fixed workspace of ufem_cg_iterate_static, one copy per device for the
+// life of the process: kStaticCgScalarBytes of CG scalars, then A p.  Host
+// code never passes this name to a kernel: it takes the device address from
+// static_scratch_address once per device (the name is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_address(void** out) { return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)); }
+
+hipError_t launch_cg_static_begin(int prec, int64_t n, const void* r, double* scal, hipStream_t s) {
+  cg_clear4_kernel<<<1, 64, 0, s>>>(scal);
+  if (n > 0) {
+    if (prec == 0)
+      dot_kernel<double><<<grid_for(n), 256, 0, s>>>(n, (const double*)r, (const double*)r, scal);
+    else
+      dot_kernel<float><<<grid_for(n), 256, 0, s>>>(n, (const float*)r, (const float*)r, scal);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_static_end(const double* scal, double* out, hipStream_t s) {
+  cg_result_kernel<<<1, 64, 0, s>>>(scal, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const void* ap, double* scal, hipStream_t s) {
   const int g = grid_for(n);

@@ -134,6 +134,16 @@ hipError_t launch_operator(const DevArgs<T>& a, int dim, int degree, const T* u,
 
 hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const void* ap, double* scal,
                            hipStream_t s);
+// Static workspace of ufem_cg_iterate_static (blas.hip): 64 MiB for A p after
+// 256 bytes of CG scalars.  static_scratch_address gives the calling
+// thread's current device's copy.
+constexpr size_t kStaticCgScalarBytes = 256;
+constexpr size_t kStaticScratchBytes = (size_t(64) << 20) + kStaticCgScalarBytes;
+hipError_t static_scratch_address(void** out);
+// scal[0..3] := (r.r, 0, 0, 0)
+hipError_t launch_cg_static_begin(int prec, int64_t n, const void* r, double* scal, hipStream_t s);
+// out[0] := scal[0] (r.r), out[1] := scal[3] (breakdown flag)
+hipError_t launch_cg_static_end(const double* scal, double* out, hipStream_t s);
 
 hipError_t launch_dot(int prec, int64_t n, const void* x, const void* y, double* out, hipStream_t s);
 hipError_t launch_axpby(int prec, int64_t n, double a, const void* x, double b, void* y, hipStream_t s);
