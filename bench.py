@@ -16,6 +16,11 @@ that every apply streams its vectors from HBM.
 throughput metric, Section 5.1: DoFs / time of one operator evaluation); the
 FP32 and adjoint throughputs are reported beside it.  Every kernel of a step is
 bracketed by HIP events on the stream the library launches on.
+
+Beside the timed steps (not timed): the error of the FP64 and FP32 applies and
+of the adjoint pass against the FP64 oracle on sampled rows, the oracle's own
+throughput on one core and on every core of the process (at most 16), and
+the solve of A u = b to 1e-10 by FP64 CG and by FP32-inner defect correction.
 """
 from __future__ import annotations
 
@@ -27,6 +32,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -35,6 +42,11 @@ METRIC = "operator DoF/s (3D DG k=3, FP64 vs FP32) + adjoint DoF/s; % of HBM roo
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64, published
 KERNEL_SOURCES = ["paper_2404_07911_amd/csrc/kernels_impl.hpp", "paper_2404_07911_amd/csrc/device.hpp"]
+
+
+def progress(msg):
+    """a line on stderr per stage, so that a long run shows it is alive"""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -54,9 +66,10 @@ STAGE_KERNELS = {
     "cut_lines": "cut_batch_kernel (volume and interface lines)",
     "cut_face_lines": "cut_face_kernel (cut-face lines)",
 }
+STAGE_KERNELS_MIXED = dict(STAGE_KERNELS, cut_lines="cut_matrix_kernel (element matrices of the cut cells)")
 
 
-def model(info, dim, p, s, kappa=False):
+def model(info, dim, p, s, kappa=False, mixed=False):
     """Algorithmic bytes per kernel stage and model FLOPs of one apply.
 
     Bytes (s = bytes per value) count what a stage must move at the least:
@@ -86,6 +99,11 @@ def model(info, dim, p, s, kappa=False):
     }
     # the whole apply: u read and v written once per DoF, plus the point data
     b["total"] = info["n_dofs"] * 2 * s + n_vol * (dim + 1) * s + n_surf * (2 * dim + 1) * s + n_fcut * dim * s
+    if mixed:
+        # the element matrices replace the volume and interface point data
+        mat = info["n_cut"] * nd * nd * s
+        b["cut_lines"] = info["n_cut"] * nd * 3 * s + mat
+        b["total"] += mat - n_vol * (dim + 1) * s - n_surf * (2 * dim + 1) * s
     if kappa:
         k_str = (seg[1] - seg[0]) + (seg[3] - seg[2])
         b["structured"] += k_str * s
@@ -116,60 +134,183 @@ def load_counters(kernel_key):
     return ent
 
 
-def cpu_baseline(wl, u, seconds_target=15.0, seed=1234):
-    """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload's rows (cells in the workload's inside/cut proportion)."""
+WORKLOADS = {
+    "ball3d": lambda seed, n, degree: __import__("ufem_inputs").ball3d(seed, n=n or 64, degree=degree or 3),
+    "kappa3d": lambda seed, n, degree: __import__("ufem_inputs").kappa3d(seed, n=n or 48, degree=degree or 4),
+    "balls3d": lambda seed, n, degree: __import__("ufem_inputs").balls3d(seed, n=n or 128, degree=degree or 3),
+    "sweep3d": lambda seed, n, degree: __import__("ufem_inputs").sweep3d(degree or 3, seed, n=n),
+    "disk2d": lambda seed, n, degree: __import__("ufem_inputs").disk2d(seed, n=n or 16, degree=degree or 2),
+}
+
+
+def make_workload(name, seed, n=None, degree=None, layer=None):
+    import ufem_inputs as ui
+
+    if name == "plane3d":
+        return ui.plane3d(layer if layer is not None else 1, seed, n=n or 128, degree=degree or 1)
+    return WORKLOADS[name](seed, n, degree)
+
+
+def _oracle(wl):
+    from oracle.operator import UnfittedDG
+
+    return UnfittedDG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi, plane=wl.plane)
+
+
+def _prepare_rules(ora, cells):
+    """quadrature generation is setup, not timed"""
+    cellset = set(int(b) for b in cells)
+    for b in cellset:
+        if ora.cls[b] == 1:
+            ora.cell_rule(b)
+    for fi, f in enumerate(ora.faces):
+        if f[3] == "cut" and (f[0] in cellset or f[1] in cellset):
+            ora.face_rule(fi)
+
+
+def _oracle_worker(spec):
+    """One process of the all-cores oracle run: the workload's oracle, the
+    seeded u, its share of the sampled cells; times the apply on them once
+    every worker is ready."""
+    import numpy as np
+
+    import ufem_inputs as ui
+
+    wl, rng = make_workload(spec["workload"], spec["seed"], spec["n"], spec["degree"], spec["layer"])
+    ora = _oracle(wl)
+    u = ui.uniform_vector(rng, ora.n_dofs)
+    cells = spec["cells"]
+    _prepare_rules(ora, cells)
+    spec["barrier"].wait()
+    t0 = time.perf_counter()
+    v = ora.apply(u, cells=cells)
+    dt = time.perf_counter() - t0
+    rows = np.concatenate([v[ora.rank[b] * ora.nd:(ora.rank[b] + 1) * ora.nd] for b in cells]) if cells else v[:0]
+    return len(cells) * ora.nd, dt, rows
+
+
+def cpu_baseline(args, wl, u, seconds_target=12.0, seed=1234):
+    """The FP64 oracle, as it stands, on bounded samples of the same
+    workload's rows (cells in the workload's inside / cut proportion): on one
+    core in this process, then on every core the process may use (at most
+    16), one oracle process per core, each on its share of a larger sample.
+    Returns the baseline record and the oracle rows of the one-core sample."""
+    import multiprocessing as mp
+
     import numpy as np
 
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
         threadpool_limits = None
-    from oracle.operator import UnfittedDG
+
+    ora = _oracle(wl)
+    rng = np.random.default_rng(seed)
+    n_in, n_cut = len(ora.inside_cells), len(ora.cut_cells)
+    frac_cut = n_cut / max(1, n_in + n_cut)
+
+    def sample(n_sample):
+        nc = min(n_cut, max(1 if n_cut else 0, int(round(n_sample * frac_cut))))
+        ni = min(n_in, max(0, n_sample - nc))
+        return [int(b) for b in rng.choice(ora.inside_cells, ni, replace=False)] + [
+            int(b) for b in rng.choice(ora.cut_cells, nc, replace=False)]
 
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
-        ora = UnfittedDG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi)
-        rng = np.random.default_rng(seed)
-        n_in, n_cut = len(ora.inside_cells), len(ora.cut_cells)
-        frac_cut = n_cut / max(1, n_in + n_cut)
-        # probe the per-cell cost, then size the sample to ~seconds_target
-        probe = list(rng.choice(ora.inside_cells, 20, replace=False)) + list(rng.choice(ora.cut_cells, 4, replace=False))
+        probe = sample(24)
+        _prepare_rules(ora, probe)
         ora.apply(u, cells=probe)
         t0 = time.perf_counter()
         ora.apply(u, cells=probe)
         per_cell = (time.perf_counter() - t0) / len(probe)
-        n_sample = int(max(24, min(n_in + n_cut, seconds_target / max(per_cell, 1e-6))))
-        nc = max(1, int(round(n_sample * frac_cut)))
-        ni = max(1, n_sample - nc)
-        cells = list(rng.choice(ora.inside_cells, min(ni, n_in), replace=False)) + list(
-            rng.choice(ora.cut_cells, min(nc, n_cut), replace=False)
-        )
-        cellset = set(int(b) for b in cells)
-        for b in cellset:  # quadrature generation is setup, not timed
-            if ora.cls[b] == 1:
-                ora.cell_rule(b)
-        for fi, f in enumerate(ora.faces):
-            if f[3] == "cut" and (f[0] in cellset or f[1] in cellset):
-                ora.face_rule(fi)
+        cells1 = sample(int(max(24, min(n_in + n_cut, seconds_target / max(per_cell, 1e-6)))))
+        _prepare_rules(ora, cells1)
         t0 = time.perf_counter()
-        ora.apply(u, cells=cells)
-        dt = time.perf_counter() - t0
-        dofs = len(cells) * ora.nd
-        return {
-            "value": dofs / dt,
-            "unit": "DoF/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"rows of {len(cells)} of {n_in + n_cut} active cells ({len(cells) - min(nc, n_cut)} inside, "
-            f"{min(nc, n_cut)} cut, seeded), {dofs} DoF, {dt:.1f} s, one thread (BLAS limited to 1)",
-        }
+        v1 = ora.apply(u, cells=cells1)
+        dt1 = time.perf_counter() - t0
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
+    dofs1 = len(cells1) * ora.nd
+    n1i = sum(1 for b in cells1 if ora.cls[b] == 0)
+    one = {"value": dofs1 / dt1, "unit": "DoF/s", "cores": 1,
+           "sample": f"rows of {len(cells1)} of {n_in + n_cut} active cells ({n1i} inside, {len(cells1) - n1i} cut, "
+                     f"seeded), {dofs1} DoF, {dt1:.1f} s, one thread (BLAS limited to 1)"}
+    out = dict(one, kind="oracle")
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    progress(f"oracle on one core: {one['value']:.3g} DoF/s")
+    if cores > 1 and not args.cpu_one_core:
+        progress(f"oracle on {cores} cores")
+        per_worker = int(max(24, seconds_target / max(dt1 / len(cells1), 1e-6)))
+        cells_all = sample(min(n_in + n_cut, per_worker * cores))
+        chunks = [cells_all[i::cores] for i in range(cores)]
+        saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+        for k in saved:
+            os.environ[k] = "1"
+        try:
+            sp = mp.get_context("spawn")
+            with sp.Manager() as mgr:
+                barrier = mgr.Barrier(cores)
+                specs = [{"workload": wl.name if wl.name != "custom" else "ball3d", "seed": args.seed, "n": args.n,
+                          "degree": args.degree, "layer": args.layer, "cells": c, "barrier": barrier} for c in chunks]
+                with sp.Pool(cores) as pool:
+                    res = pool.map(_oracle_worker, specs)
+        finally:
+            for k, val in saved.items():
+                if val is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = val
+        dofs = sum(r[0] for r in res)
+        dt = max(r[1] for r in res)
+        ni = sum(1 for b in cells_all if ora.cls[b] == 0)
+        out = {"value": dofs / dt, "unit": "DoF/s", "cores": cores, "kind": "oracle",
+               "sample": f"rows of {len(cells_all)} of {n_in + n_cut} active cells ({ni} inside, "
+                         f"{len(cells_all) - ni} cut, seeded), {dofs} DoF, {cores} oracle processes of one "
+                         f"thread each (BLAS limited to 1), {dt:.1f} s for the slowest",
+               "single_core": one}
+    rows1 = (cells1, np.concatenate([v1[ora.rank[b] * ora.nd:(ora.rank[b] + 1) * ora.nd] for b in cells1]), ora)
+    return out, rows1
 
 
-def solve_mode(args, wl, rng, plan, op, t_setup):
+def oracle_errors(wl, info, cls, v64, v32, atw, dk, rows1):
+    """Largest error against the FP64 oracle relative to the largest oracle
+    entry, on sampled rows: the stored oracle rows of the full-size
+    workloads (tests/golden, written by the oracle for the same seeded
+    inputs) when they match this workload, else the rows of the one-core
+    oracle sample (FP64 apply only).  v64, v32, atw, dk: host arrays."""
+    import numpy as np
+
+    nd = (wl.degree + 1) ** wl.dim
+    tag = f"sweep{wl.degree}" if wl.name == "sweep3d" else wl.name
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{tag}.npz")
+    rank = np.cumsum(cls != 2) - 1
+
+    def err(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    def rows(v, cells):
+        return np.stack([v[rank[b] * nd:(rank[b] + 1) * nd] for b in cells])
+
+    if os.path.exists(path):
+        ref = np.load(path)
+        if int(ref["n_dofs"]) == info["n_dofs"] and int(ref["degree"]) == wl.degree and int(ref["n"]) == wl.n:
+            cells = [int(b) for b in ref["cells"]]
+            out = {"fp64_apply": err(rows(v64, cells), ref["rows64"]),
+                   "fp32_apply": err(rows(v32, cells), ref["rows32"]),
+                   "adjoint_ATw": err(rows(atw, cells), ref["rows_adj"])}
+            if "dk_idx" in ref and dk is not None:
+                out["adjoint_dkappa"] = err(dk[ref["dk_idx"]], ref["dk_val"])
+            out["rows"] = f"{len(cells)} sampled cells, stored oracle rows (tests/golden/fullsize_{tag}.npz)"
+            return out
+    if rows1 is not None:
+        cells, ref_rows, _ = rows1
+        return {"fp64_apply": err(rows(v64, cells).reshape(-1), ref_rows),
+                "rows": f"{len(cells)} cells of the one-core oracle sample"}
+    return None
+
+
+def run_solve(op, plan, rng, tol, inner_rtol):
     """A u = b with b = A u*, u* uniform in [-1, 1]: plain FP64 CG against
     FP32-inner / FP64-outer defect correction, both to ||b - A u|| <= tol ||b||
     measured in FP64 on the GPU."""
@@ -182,39 +323,120 @@ def solve_mode(args, wl, rng, plan, op, t_setup):
     n = plan.info["n_dofs"]
     ustar = torch.from_numpy(ui.uniform_vector(rng, n)).cuda()
     b = op.apply(ustar)
-
     x = torch.zeros_like(b)
-    (x, i64), t64 = timed(lambda: device_cg(op, b, x, rtol=args.tol, maxiter=400000), ops)
+    (x, i64), t64 = timed(lambda: device_cg(op, b, x, rtol=tol, maxiter=400000), ops)
     r = op.apply(x)
     res64 = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
-    (u, idc), tdc = timed(lambda: device_defect_correction(op, b, tol=args.tol, inner_rtol=args.inner_rtol), ops)
+    (u, idc), tdc = timed(lambda: device_defect_correction(op, b, tol=tol, inner_rtol=inner_rtol), ops)
     r = op.apply(u)
     resdc = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
     err = float(torch.linalg.norm(u - ustar) / torch.linalg.norm(ustar))
-    # one adjoint pass at the solution: A^T w and dL/dkappa for w = A u - b
     w = (r - b).contiguous()
     atw = torch.empty_like(w)
     dk = torch.empty(plan.info["n_qp"], dtype=torch.float64, device=w.device)
     (_, tadj) = timed(lambda: op.apply_adjoint(w, u, atw, dk), ops)
+    return {
+        "tol": tol,
+        "speedup_fp32_inner_over_fp64": t64 / tdc,
+        "fp64_cg": {"seconds": t64, "iterations": i64["iterations"], "rel_residual": res64,
+                    "converged": i64["converged"]},
+        "defect_correction": {"seconds": tdc, "outer": idc["outer"], "inner_iterations": idc["inner_iterations"],
+                              "rel_residual": resdc, "converged": idc["converged"], "inner_rtol": inner_rtol},
+        "solution_rel_error": err,
+        "adjoint_at_solution_s": tadj,
+    }
+
+
+def workload_text(wl):
+    if wl.plane is not None:
+        geo = f"plane n={list(np.round(wl.plane[0], 6))} offset {wl.plane[1]:.6f}"
+    else:
+        geo = f"{len(wl.radii)} ball(s)"
+    return (f"{wl.name}: {wl.dim}D SIPG DG p={wl.degree}, {wl.n}^{wl.dim} background cells on [-1,1]^{wl.dim}, "
+            f"{geo}, Nitsche + face ghost penalty" + (", kappa field" if wl.name == "kappa3d" else ""))
+
+
+def solve_mode(args, wl, rng, plan, op, t_setup):
+    """--mode solve: the solve comparison of run_solve as its own line."""
+    n = plan.info["n_dofs"]
+    sol = run_solve(op, plan, rng, args.tol, args.inner_rtol)
     out = {
         "metric": "solve time to 1e-10 relative residual, FP64 CG vs FP32-inner defect correction",
-        "value": t64 / tdc,
+        "value": sol["speedup_fp32_inner_over_fp64"],
         "unit": "speedup",
         "higher_is_better": True,
         "n_gpus": 1,
         "dtype": "f64/f32",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.dim}D SIPG DG p={wl.degree}, {wl.n}^{wl.dim} background cells, "
-                               f"{len(wl.radii)} ball(s)" + (", kappa field" if wl.name == "kappa3d" else ""),
-                   "active_dofs": n, "degree": wl.degree, "background_cells": wl.n},
-        "fp64_cg": {"seconds": t64, "iterations": i64["iterations"], "rel_residual": res64,
-                    "converged": i64["converged"]},
-        "defect_correction": {"seconds": tdc, "outer": idc["outer"], "inner_iterations": idc["inner_iterations"],
-                              "rel_residual": resdc, "converged": idc["converged"], "history": idc["history"],
-                              "inner_rtol": args.inner_rtol},
-        "solution_rel_error": err,
-        "adjoint_at_solution_s": tadj,
+        "config": {"workload": workload_text(wl), "active_dofs": n, "degree": wl.degree, "background_cells": wl.n},
+        **{k: v for k, v in sol.items() if k != "speedup_fp32_inner_over_fp64"},
         "setup_s": t_setup,
+        "kernel_hash": kernel_hash(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def plane_sweep_mode(args):
+    """Throughput against the ratio of cut to physical cells (the plane
+    benchmark, Section 5.2): the domain below a plane in cell layer L of an
+    n^3 mesh (ratio 1 / (L + 1); no cut cell for L >= n), FP64 and FP32
+    applies timed with HIP events, vectors resident in HBM."""
+    import torch
+
+    import ufem_inputs as ui
+    from paper_2404_07911_amd import Operator, Plan, Problem
+
+    n = args.n or 128
+    degrees = [args.degree] if args.degree else [1, 3]
+    layers = [0, 1, 9, 99, n]
+    stream = torch.cuda.current_stream()
+    points = []
+    for p in degrees:
+        for layer in layers:
+            wl, rng = ui.plane3d(layer, args.seed, n=n, degree=p)
+            plan = Plan(Problem.from_workload(wl))
+            op = Operator(plan, device=0)
+            info = plan.info
+            nd = info["n_dofs"]
+            u = torch.from_numpy(ui.uniform_vector(rng, nd)).cuda()
+            rec = {"degree": p, "layer": layer, "active_cells": info["n_active"], "cut_cells": info["n_cut"],
+                   "cut_cell_ratio": info["n_cut"] / max(1, info["n_active"]), "active_dofs": nd}
+            for name, x in (("fp64", u), ("fp32", u.to(torch.float32))):
+                pairs = max(2, int(math.ceil(args.cache_bytes / (2 * x.element_size() * nd))))
+                X = [x.clone() for _ in range(pairs)]
+                V = [torch.empty_like(x) for _ in range(pairs)]
+                for i in range(args.warmup):
+                    op.apply(X[i % pairs], V[i % pairs])
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(args.steps)]
+                torch.cuda.synchronize()
+                for i in range(args.steps):
+                    ev[i][0].record(stream)
+                    op.apply(X[i % pairs], V[i % pairs])
+                    ev[i][1].record(stream)
+                torch.cuda.synchronize()
+                ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+                rec[f"{name}_apply_ms"] = ms
+                rec[f"{name}_dofs_per_s"] = nd / (ms * 1e-3)
+                del X, V
+            print(f"plane sweep p={p} layer={layer}: ratio {rec['cut_cell_ratio']:.3f}, {nd} DoF, "
+                  f"FP64 {rec['fp64_dofs_per_s'] / 1e9:.1f} GDoF/s", file=sys.stderr, flush=True)
+            points.append(rec)
+            del op, plan, u
+            torch.cuda.empty_cache()
+    out = {
+        "metric": "operator DoF/s against the cut-cell ratio (plane benchmark)",
+        "value": None,
+        "unit": "DoF/s",
+        "higher_is_better": True,
+        "n_gpus": 1,
+        "dtype": "f64/f32",
+        "data": "synthetic",
+        "config": {"workload": f"plane3d: 3D SIPG DG, {n}^3 background cells on [-1,1]^3, domain below a plane "
+                               f"z ~ const (normal tilted by {ui.PLANE_TILT}) in cell layer L, "
+                               f"Nitsche + face ghost penalty", "background_cells": n},
+        "points": points,
         "kernel_hash": kernel_hash(),
     }
     print(json.dumps(out), flush=True)
@@ -226,16 +448,24 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="ball3d", choices=["ball3d", "kappa3d", "balls3d", "sweep3d", "disk2d"])
+    ap.add_argument("--workload", default="ball3d",
+                    choices=["ball3d", "kappa3d", "balls3d", "sweep3d", "disk2d", "plane3d"])
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--layer", type=int, default=None,
+                    help="plane3d: cell layer of the plane (cut-cell ratio 1 / (layer + 1); >= n: no cut)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cache-bytes", type=float, default=640e6, help="total bytes of rotated vector pairs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-one-core", action="store_true", help="oracle baseline on one core only")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve comparison of the default line")
+    ap.add_argument("--mixed", action="store_true",
+                    help="mixed evaluation: the cut cells' volume and interface terms as precomputed element matrices")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--mode", default="apply", choices=["apply", "solve"],
-                    help="apply: operator throughput (default); solve: FP64 CG vs FP32-inner defect correction")
+    ap.add_argument("--mode", default="apply", choices=["apply", "solve", "plane-sweep"],
+                    help="apply: operator throughput (default); solve: FP64 CG vs FP32-inner defect correction; "
+                         "plane-sweep: throughput against the cut-cell ratio (plane benchmark)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args(argv)
@@ -248,7 +478,6 @@ def main(argv=None):
         )
         return 2
 
-    import numpy as np
     import torch
 
     import ufem_inputs as ui
@@ -256,18 +485,12 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.mode == "plane-sweep":
+        return plane_sweep_mode(args)
 
-    if args.workload == "ball3d":
-        wl, rng = ui.ball3d(args.seed, n=args.n or 64, degree=args.degree or 3)
-    elif args.workload == "kappa3d":
-        wl, rng = ui.kappa3d(args.seed, n=args.n or 48, degree=args.degree or 4)
-    elif args.workload == "balls3d":
-        wl, rng = ui.balls3d(args.seed, n=args.n or 128, degree=args.degree or 3)
-    elif args.workload == "sweep3d":
-        wl, rng = ui.sweep3d(args.degree or 3, args.seed, n=args.n)
-    else:
-        wl, rng = ui.disk2d(args.seed, n=args.n or 16, degree=args.degree or 2)
+    wl, rng = make_workload(args.workload, args.seed, args.n, args.degree, args.layer)
 
+    progress(f"plan and setup of {wl.name} p={wl.degree} n={wl.n}")
     t0 = time.perf_counter()
     plan = Plan(Problem.from_workload(wl))
     op = Operator(plan, device=0)
@@ -278,6 +501,11 @@ def main(argv=None):
     if with_kappa:
         # variable coefficient at every quadrature point (the kappa workload)
         op.set_kappa(torch.from_numpy(ui.kappa_field(plan.qp()[0])).to(dev))
+    if args.mixed:
+        progress("element matrices of the cut cells (mixed evaluation)")
+        t0 = time.perf_counter()
+        op.set_mixed(True)
+        t_setup += time.perf_counter() - t0
     if args.mode == "solve":
         return solve_mode(args, wl, rng, plan, op, t_setup)
     u_host = ui.uniform_vector(rng, n)
@@ -316,6 +544,7 @@ def main(argv=None):
         if ev is not None:
             ev[2 * NS + 1].record(stream)
 
+    progress("warmup and timed steps")
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -339,13 +568,19 @@ def main(argv=None):
     t32 = mean_ms(NS, 2 * NS) * 1e-3
     tadj = adj * 1e-3
 
-    # correctness spot check of the timed FP64 result against a fresh apply
-    vchk = op.apply(U64[0])
-    torch.cuda.synchronize()
-    assert torch.isfinite(vchk).all()
+    # the results of the timed configuration on the first pair, for the
+    # error against the oracle
+    v64_h = op.apply(U64[0]).cpu().numpy()
+    v32_h = op.apply(U32[0]).cpu().numpy().astype(np.float64)
+    op.apply_adjoint(W64, U64[0], ATW, DK)
+    atw_h, dk_h = ATW.cpu().numpy(), DK.cpu().numpy()
+    assert np.isfinite(v64_h).all() and np.isfinite(v32_h).all() and np.isfinite(atw_h).all()
+    if not args.no_solve:
+        progress("solve: FP64 CG and FP32-inner defect correction")
+    sol = None if args.no_solve else run_solve(op, plan, rng, args.tol, args.inner_rtol)
 
-    bytes64, flops = model(info, wl.dim, wl.degree, 8, with_kappa)
-    bytes32, _ = model(info, wl.dim, wl.degree, 4, with_kappa)
+    bytes64, flops = model(info, wl.dim, wl.degree, 8, with_kappa, args.mixed)
+    bytes32, _ = model(info, wl.dim, wl.degree, 4, with_kappa, args.mixed)
     dom = max(ms64, key=ms64.get)
     dom_ms = ms64[dom]
     achieved = bytes64[dom] / (dom_ms * 1e-3) / 1e9
@@ -353,7 +588,7 @@ def main(argv=None):
     traffic = ctr["hbm_bytes_per_launch"] if ctr else None
     roofline = {
         "bound": "hbm",
-        "kernel": f"{STAGE_KERNELS[dom]}, K={wl.degree + 1}, D={wl.dim}, double",
+        "kernel": f"{(STAGE_KERNELS_MIXED if args.mixed else STAGE_KERNELS)[dom]}, K={wl.degree + 1}, D={wl.dim}, double",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -377,8 +612,7 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{wl.name}: {wl.dim}D SIPG DG p={wl.degree}, {wl.n}^{wl.dim} background cells on [-1,1]^{wl.dim}, "
-            f"{len(wl.radii)} ball(s), Nitsche + face ghost penalty",
+            "workload": workload_text(wl),
             "degree": wl.degree,
             "background_cells": wl.n,
             "active_dofs": n,
@@ -386,6 +620,9 @@ def main(argv=None):
             "kappa": "1 + 0.5 sin(pi x) sin(pi y) sin(pi z) per quadrature point" if with_kappa else "1",
             "inside_cells": info["n_inside"],
             "cut_cells": info["n_cut"],
+            "cut_cell_ratio": info["n_cut"] / max(1, info["n_active"]),
+            "evaluation": "mixed (cut-cell volume and interface terms as element matrices)" if args.mixed
+            else "matrix-free",
             "quadrature_points": info["n_qp"],
             "parallelism": "single GPU",
         },
@@ -420,9 +657,15 @@ def main(argv=None):
         torch.cuda.synchronize()
         out["copy_probe"] = {"bytes_read": a.numel() * 8, "ms": e0.elapsed_time(e1),
                              "gbs": 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9}
+    rows1 = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, u_host, args.cpu_seconds)
+        progress("oracle baseline on the host cores")
+        out["cpu_baseline"], rows1 = cpu_baseline(args, wl, u_host, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
+    out["error_vs_oracle"] = oracle_errors(wl, info, plan.cells(), v64_h, v32_h, atw_h,
+                                           dk_h, rows1)
+    if sol is not None:
+        out["solve"] = sol
     print(json.dumps(out), flush=True)
     return 0
 

@@ -85,6 +85,17 @@ typedef struct ufem_op ufem_op;     /* device-side operator */
  * phi = (n . x - offset) / |n| (the plane benchmark of Section 5.2). */
 enum { UFEM_LEVELSET_BALLS = 0, UFEM_LEVELSET_PLANE = 1 };
 
+/* Ghost-penalty kinds of ufem_problem.gp_kind.  FACE: the face ghost
+ * penalty sum_j gamma_j h^(2j-1) ([d_n^j v], [d_n^j u])_F on every face of
+ * a cut cell.  VOLUME: the volume ghost penalty of Section 2.2 (eq.
+ * volume_based_gp), (tau_v / h^2) (J_P v, J_P u)_P over patches P of two
+ * face neighbours, J_P u the difference of the two cells' polynomials
+ * extended over the patch, tau_v = gp_gamma; patches by the stable-neighbour
+ * strategy (each cut cell with its neighbour of largest volume fraction,
+ * fractions within 1e-10 equal, the lower slot 2 axis + side first).
+ * VOLUME_ALL: the same term on every face of a cut cell. */
+enum { UFEM_GP_FACE = 0, UFEM_GP_VOLUME = 1, UFEM_GP_VOLUME_ALL = 2 };
+
 /* Problem description.  All pointers are host pointers read during
  * ufem_plan_create only.  The physical domain is {phi < 0}. */
 typedef struct {
@@ -100,13 +111,15 @@ typedef struct {
   const double* radii;   /* BALLS: host, n_balls, > 0 */
   double nitsche_factor; /* tau_D = nitsche_factor * p^2 (Section 2.1) */
   double sipg_factor;    /* gamma = sipg_factor * p^2, SIPG penalty gamma/h */
-  double gp_gamma;       /* ghost penalty weight */
-  int32_t gp_jmin;       /* lowest normal-derivative order penalised, 0..p */
-  int32_t gp_flat;       /* 0: gamma_j = gp_gamma/(j!)^2, 1: gamma_j = gp_gamma */
+  double gp_gamma;       /* ghost penalty weight (tau_v of the volume kinds) */
+  int32_t gp_jmin;       /* face kind: lowest derivative order penalised, 0..p */
+  int32_t gp_flat;       /* face kind: 0: gamma_j = gp_gamma/(j!)^2, 1: gp_gamma */
   int32_t levelset;      /* UFEM_LEVELSET_BALLS (0, the zero-initialised
                             default) or UFEM_LEVELSET_PLANE */
   double plane_normal[3];/* PLANE: normal n (first dim entries, nonzero) */
   double plane_offset;   /* PLANE: offset; phi = (n . x - offset) / |n| */
+  int32_t gp_kind;       /* UFEM_GP_FACE (0, default), UFEM_GP_VOLUME or
+                            UFEM_GP_VOLUME_ALL */
 } ufem_problem;
 
 typedef struct {
@@ -183,6 +196,21 @@ int ufem_plan_import_quadrature(ufem_plan* plan, const int64_t* vol_count, const
 int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_device_bytes, ufem_op** out);
 int ufem_destroy(ufem_op* op);
 int ufem_info_op(const ufem_op* op, ufem_info* info);
+
+/* Mixed evaluation (Section 3.2, eq. additive_decomp, the "mixed" option):
+ * enable != 0 precomputes the cut cells' unstructured cell terms (volume and
+ * interface quadrature) as one dense nd x nd element matrix per cut cell
+ * (nd = (p+1)^dim; built on `stream` from the matrix-free line kernels
+ * applied to unit vectors, float64, rounded once for the float32 operator),
+ * and later applies, adjoint passes and CG iterations apply them as a
+ * batched matrix-vector product; structured terms and cut faces stay
+ * matrix-free.  Device memory: n_cut nd^2 (8 + 4) bytes, allocated at the
+ * first enable and counted against max_device_bytes (ENOMEM beyond), plus
+ * two temporary vectors during the build.  The matrices follow
+ * ufem_set_terms and ufem_set_kappa (float64 kappa; rebuilt there, which
+ * synchronises the stream).  enable == 0 returns to the matrix-free
+ * evaluation (the memory stays until ufem_destroy).  Synchronous. */
+int ufem_set_mixed(ufem_op* op, int32_t enable, void* stream);
 
 /* Select the terms of subsequent applies and adjoint passes (default
  * UFEM_TERM_ALL). */

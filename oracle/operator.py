@@ -21,6 +21,25 @@ The face ghost penalty is only referred to (its treatment lives in a
 supplement that is not part of the text); the form above is the standard face
 ghost penalty of Burman (2010), with the weights as stated.
 
+With gp_kind='volume' the ghost penalty is instead the volume-based one of
+Section 2.2 (eq. volume_based_gp), the paper's own choice:
+
+  g_v(v, u) = sum over patches P of (tau_v / h^2) (J_P v, J_P u)_P,
+
+a patch being two face neighbours E1, E2 and J_P u the difference of the two
+cells' polynomials, each extended to the whole patch (u1 - E u2 on E1 and
+E u1 - u2 on E2, E the extension of a cell's polynomial to its neighbour).
+As in Section 3.3 the extension is evaluated by shifting the Gauss points of
+one cell into the reference coordinates of the other (values of the Lagrange
+basis outside [0, 1]), and the integrals use the k^d Gauss rule of each
+whole cell.  Patches (stable-neighbour strategy of Section 2.2): every cut
+cell is paired with the face neighbour of largest volume fraction |N cap
+Omega| / |N| (1 for inside cells; for cut cells the sum of the reference
+weights of their volume rule), fractions within 1e-10 counting as equal and
+the lower slot 2 axis + side winning; a patch chosen by both of its cells
+counts once.  gp_kind='volume_all' takes every face of a cut cell instead
+(all-neighbours strategy).  tau_v is gp_gamma.
+
 Every term is evaluated on the reference cell [0, 1]^d: with x = x_0 + h xi
 every term scales with h^(d-2) (gradients carry 1/h, volumes h^d, faces and
 the interface h^(d-1), penalties 1/h, the j-th ghost-penalty derivative
@@ -78,6 +97,7 @@ class UnfittedDG:
         gp_jmin=0,
         gp_weights="factorial",
         plane=None,
+        gp_kind="face",
     ):
         self.dim = dim
         self.p = degree
@@ -109,6 +129,10 @@ class UnfittedDG:
         self.inside_cells = [int(b) for b in self.active if self.cls[b] == INSIDE]
         self.cut_cells = [int(b) for b in self.active if self.cls[b] == CUT]
         self.faces = active_faces(self.mesh, self.balls, self.cls)
+        if gp_kind not in ("face", "volume", "volume_all"):
+            raise ValueError(gp_kind)
+        self.gp_kind = gp_kind
+        self.tau_v = gp_gamma
         self._cell_rules = {}
         self._face_rules = {}
         self._layout = None
@@ -117,6 +141,40 @@ class UnfittedDG:
         for fi, (bm, bp, a, kind, gp) in enumerate(self.faces):
             self.cell_faces[bm].append(fi)
             self.cell_faces[bp].append(fi)
+        if gp_kind == "volume":
+            patch = self.stable_patches()
+            self.faces = [(bm, bp, a, kind, fi in patch) for fi, (bm, bp, a, kind, gp) in enumerate(self.faces)]
+
+    def volume_fraction(self, b):
+        """|T cap Omega| / |T|: 1 for inside cells, the sum of the reference
+        weights of the volume rule for cut cells."""
+        if self.cls[b] == INSIDE:
+            return 1.0
+        return float(np.sum(self.cell_rule(b)[1]))
+
+    def stable_patches(self):
+        """Face indices of the stable-neighbour patches: each cut cell with
+        its face neighbour of largest volume fraction (slots 2 axis + side in
+        increasing order, a later slot winning only by more than 1e-10)."""
+        out = set()
+        for b in self.cut_cells:
+            ijk = self.mesh.index_to_ijk(b)
+            best, best_f, best_fi = None, 0.0, None
+            for a in range(self.dim):
+                for side in (0, 1):
+                    if (side == 0 and ijk[a] == 0) or (side == 1 and ijk[a] == self.mesh.n - 1):
+                        continue
+                    nb = b + (1 if side else -1) * self.mesh.strides[a]
+                    if self.cls[nb] == OUTSIDE:
+                        continue
+                    fr = self.volume_fraction(nb)
+                    if best is None or fr > best_f + 1e-10:
+                        lo_c, hi_c = (b, nb) if side else (nb, b)
+                        fi = next(f for f in self.cell_faces[b] if self.faces[f][0] == lo_c and self.faces[f][1] == hi_c)
+                        best, best_f, best_fi = nb, fr, fi
+            if best_fi is not None:
+                out.add(best_fi)
+        return out
 
     # ---------------------------------------------------------------- rules
     def cell_rule(self, b):
@@ -382,7 +440,9 @@ class UnfittedDG:
                         wjump = Pm @ wm - Pp @ wp
                         wavg = 0.5 * (Dm @ wm + Dp @ wp)
                         dk[o : o + n] += s * wf * (-wavg * jump - wjump * avg + self.gamma * wjump * jump)
-            if mask & GP and gp:
+            if mask & GP and gp and self.gp_kind != "face":
+                self._volume_gp(fi, um, up, v, targets)
+            elif mask & GP and gp:
                 xf, wf = self.full_face_rule()
                 Xm = self._face_points(xf, a, 1.0)
                 Xp = self._face_points(xf, a, 0.0)
@@ -400,6 +460,25 @@ class UnfittedDG:
                     if bp in targets:
                         self._block(v, bp)[:] -= Dp.T @ (c * jump)
         return v, dk
+
+    def _volume_gp(self, fi, um, up, v, targets):
+        """The patch of face fi (lower cell bm, upper cell bp at +e_axis):
+        tau_v h^(d-2) sum over both cells' Gauss points of w J(phi_i) J(u),
+        J u = u_bm - u_bp with each polynomial evaluated at the point in its
+        own reference coordinates (the shifted points)."""
+        bm, bp, a, kind, gp = self.faces[fi]
+        xi, wq = self.full_cell_rule()
+        shift = np.zeros(self.dim)
+        shift[a] = 1.0
+        c = self.tau_v * self.h ** (self.dim - 2) * wq
+        for pts_m in (xi, xi + shift):  # the Gauss points of bm, then of bp, in bm's coordinates
+            Pm = self.basis(pts_m)
+            Pp = self.basis(pts_m - shift)
+            jump = Pm @ um - Pp @ up
+            if bm in targets:
+                self._block(v, bm)[:] += Pm.T @ (c * jump)
+            if bp in targets:
+                self._block(v, bp)[:] -= Pp.T @ (c * jump)
 
     # ------------------------------------------------------------ utilities
     def dof_values_of(self, fn):

@@ -11,6 +11,7 @@ UFEM_OK, UFEM_EINVAL, UFEM_ENOMEM, UFEM_EHIP, UFEM_EUNSUPPORTED, UFEM_ESTATE = 0
 TERM_VOLUME, TERM_SIPG, TERM_NITSCHE, TERM_GHOST, TERM_ALL = 1, 2, 4, 8, 15
 F64, F32 = 0, 1
 LEVELSET_BALLS, LEVELSET_PLANE = 0, 1
+GP_FACE, GP_VOLUME, GP_VOLUME_ALL = 0, 1, 2
 PART_INSIDE, PART_CUT_STRUCTURED, PART_CUT_LINES, PART_CUT_FACE_LINES = 1, 2, 4, 8
 PART_CUT, PART_ALL = 14, 15
 
@@ -35,6 +36,7 @@ class ufem_problem(C.Structure):
         ("levelset", C.c_int32),
         ("plane_normal", C.c_double * 3),
         ("plane_offset", C.c_double),
+        ("gp_kind", C.c_int32),
     ]
 
 
@@ -83,6 +85,7 @@ _SIGS = {
     "ufem_info_op": (C.c_int, [_vp, C.POINTER(ufem_info)]),
     "ufem_set_terms": (C.c_int, [_vp, C.c_int32]),
     "ufem_set_max_blocks": (C.c_int, [_vp, C.c_int32]),
+    "ufem_set_mixed": (C.c_int, [_vp, C.c_int32, _vp]),
     "ufem_set_kappa": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
     "ufem_apply": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "ufem_apply_part": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]),

@@ -128,6 +128,33 @@ std::vector<double> make_tables(const ufem::Plan& P) {
       }
     for (int i = 0; i < K; ++i) t[ufem::TabOff::DS(K) + q * K + i] = dl[K + i];
   }
+  if (P.gp_kind != UFEM_GP_FACE) {
+    // volume ghost penalty: tau_v times the 1D mass matrices of the own basis
+    // with itself and with the neighbour's basis over the two-cell patch
+    // (neighbour at [1, 2] for side 1, at [-1, 0] for side 0, in the own
+    // cell's coordinates), by the K-point Gauss rule on each half (exact)
+    const double tv = P.prob.gp_gamma;
+    std::vector<double> lo_, ln_;
+    for (int s = 0; s < 2; ++s) {
+      const double sh = s ? 1.0 : -1.0;  // neighbour coordinate = x - sh
+      double* Go = &t[ufem::TabOff::GP(K) + (2 * s) * K * K];
+      double* Gn = Go + K * K;
+      for (int half = 0; half < 2; ++half) {
+        const double off = half ? sh : 0.0;  // the own cell, then the neighbour's cell
+        for (int q = 0; q < K; ++q) {
+          const double x = off + gx[q];
+          ufem::lagrange_all(xl, x, 0, lo_);
+          ufem::lagrange_all(xl, x - sh, 0, ln_);
+          for (int l = 0; l < K; ++l)
+            for (int m = 0; m < K; ++m) {
+              Go[l * K + m] += tv * gw[q] * lo_[l] * lo_[m];
+              Gn[l * K + m] += tv * gw[q] * lo_[l] * ln_[m];
+            }
+        }
+      }
+    }
+    return t;
+  }
   // ghost penalty of a face, folded over the derivative orders j
   for (int s = 0; s < 2; ++s) {
     const double* Eo = &t[s ? ufem::TabOff::E1(K) : ufem::TabOff::E0(K)];
@@ -163,6 +190,9 @@ struct ufem_op {
   int32_t *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr, *fdesc = nullptr, *kinfo_inside = nullptr,
           *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
+  int32_t* cut_rank = nullptr;      // active ranks of the cut cells
+  void* cmat[2] = {nullptr, nullptr};  // mixed evaluation: element matrices per precision
+  bool mixed = false;
   // per-precision data
   struct Prec {
     void *vol_x = nullptr, *vol_w = nullptr, *surf_x = nullptr, *surf_w = nullptr, *surf_n = nullptr,
@@ -266,12 +296,15 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   for (int i = 0; i < 6; ++i) a.seg[i] = P.seg[i];
   a.tab = (const T*)d.tab;
   a.kappa = d.has_kappa ? (const T*)d.kappa : nullptr;
+  a.cut_rank = cut_rank;
+  a.cmat = mixed ? (const T*)cmat[&d == &prec[0] ? 0 : 1] : nullptr;
   a.hs = (T)std::pow(P.h, P.dim - 2);
   a.tau = (T)P.tau;
   a.gamma = (T)P.gamma;
   a.terms = terms;
   a.parts = 15;
   a.max_blocks = max_blocks;
+  a.gp_volume = P.gp_kind != UFEM_GP_FACE ? 1 : 0;
   return a;
 }
 
@@ -618,12 +651,14 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     std::vector<int32_t> vb, vl, fb, fl;
     make_batches(false, vb, vl, op->n_vbatch);
     make_batches(true, fb, fl, op->n_fbatch);
+
     if (batch_overflow) {
       delete op;
       return fail(UFEM_EUNSUPPORTED, "ufem_setup: a cut cell has more lines or cut faces than one line batch holds");
     }
     int rc;
-    if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
+    if ((rc = op->upload((void**)&op->inside, P.inside)) || (rc = op->upload((void**)&op->cut_rank, P.cut)) ||
+        (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
         (rc = op->upload((void**)&op->kinfo_all, kall)) || (rc = op->upload((void**)&op->kface_inside, kfin)) ||
         (rc = op->upload((void**)&op->kface_cut, kfcu)) ||
         (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
@@ -663,6 +698,62 @@ int ufem_info_op(const ufem_op* op, ufem_info* info) {
   return UFEM_OK;
 }
 
+// (Re)build the element matrices of the mixed evaluation: column j of every
+// cut cell's matrix is the stage-4 (volume and interface lines) result of the
+// unit vector e_j in every cut cell, with the current kappa and term mask;
+// float64 matrices, rounded once to float32 for the float32 operator.
+static int build_mixed(ufem_op* op, hipStream_t st) {
+  const ufem::Plan& P = op->P;
+  const int nd = P.nd();
+  const int ncut = (int)P.cut.size();
+  const int64_t n = P.n_dofs();
+  const int64_t nm = (int64_t)ncut * nd * nd;
+  if (ncut == 0) return UFEM_OK;
+  int rc;
+  if (!op->cmat[0]) {
+    if ((rc = op->alloc(&op->cmat[0], (size_t)nm * sizeof(double)))) return rc;
+    if ((rc = op->alloc(&op->cmat[1], (size_t)nm * sizeof(float)))) return rc;
+  }
+  void *x = nullptr, *v = nullptr;
+  hipError_t e = hipMalloc(&x, (size_t)n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&v, (size_t)n * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipFree(x);
+    return hipfail(e, "ufem_set_mixed: hipMalloc");
+  }
+  const bool was = op->mixed;
+  op->mixed = false;  // the columns come from the matrix-free line kernels
+  auto a = op->args<double>(op->prec[0]);
+  op->mixed = was;
+  a.parts = 4;
+  for (int j = 0; j < nd && e == hipSuccess; ++j) {
+    e = ufem::launch_unit_rows(0, n, nd, ncut, op->cut_rank, j, x, st);
+    if (e == hipSuccess) e = ufem::launch_zero(0, n, v, st);
+    if (e == hipSuccess)
+      e = ufem::launch_operator<double>(a, P.dim, P.p, (const double*)x, (double*)v, nullptr, nullptr, false, st);
+    if (e == hipSuccess) e = ufem::launch_matrix_column(0, nd, ncut, op->cut_rank, j, v, op->cmat[0], st);
+  }
+  if (e == hipSuccess) e = ufem::launch_matrix_cast(nm, (const double*)op->cmat[0], (float*)op->cmat[1], st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(x);
+  (void)hipFree(v);
+  if (e != hipSuccess) return hipfail(e, "ufem_set_mixed: element matrices");
+  return UFEM_OK;
+}
+
+int ufem_set_mixed(ufem_op* op, int32_t enable, void* stream) {
+  if (!op) return fail(UFEM_EINVAL, "ufem_set_mixed: null op");
+  DeviceGuard g(op->device);
+  if (!enable) {
+    op->mixed = false;
+    return UFEM_OK;
+  }
+  const int rc = build_mixed(op, (hipStream_t)stream);
+  if (rc != UFEM_OK) return rc;
+  op->mixed = true;
+  return UFEM_OK;
+}
+
 int ufem_set_max_blocks(ufem_op* op, int32_t max_blocks) {
   if (!op) return fail(UFEM_EINVAL, "ufem_set_max_blocks: null op");
   if (max_blocks < 0) return fail(UFEM_EINVAL, "ufem_set_max_blocks: max_blocks < 0");
@@ -674,6 +765,10 @@ int ufem_set_terms(ufem_op* op, int32_t mask) {
   if (!op) return fail(UFEM_EINVAL, "ufem_set_terms: null op");
   if (mask < 0 || mask > UFEM_TERM_ALL) return fail(UFEM_EINVAL, "ufem_set_terms: bad mask");
   op->terms = mask;
+  if (op->mixed) {
+    DeviceGuard g(op->device);
+    return build_mixed(op, nullptr);
+  }
   return UFEM_OK;
 }
 
@@ -684,12 +779,14 @@ int ufem_set_kappa(ufem_op* op, int32_t precision, const void* kappa, void* stre
   auto& d = op->prec[precision];
   if (!kappa) {
     d.has_kappa = false;
+    if (op->mixed && precision == UFEM_F64) return build_mixed(op, (hipStream_t)stream);
     return UFEM_OK;
   }
   size_t bytes = (size_t)op->P.seg[5] * (precision == UFEM_F64 ? 8 : 4);
   hipError_t e = hipMemcpyAsync(d.kappa, kappa, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(e, "ufem_set_kappa");
   d.has_kappa = true;
+  if (op->mixed && precision == UFEM_F64) return build_mixed(op, (hipStream_t)stream);
   return UFEM_OK;
 }
 

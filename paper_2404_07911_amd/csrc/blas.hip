@@ -216,3 +216,75 @@ hipError_t launch_zero(int prec, int64_t n, void* y, hipStream_t s) {
 }
 
 }  // namespace ufem
+
+// ------------------------------------------- mixed evaluation set-up
+namespace ufem {
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(256) unit_rows_kernel(int64_t n_dofs, int nd, int n_cut,
+                                                        const int32_t* __restrict__ cut_rank, int j, T* __restrict__ x) {
+  // zero everywhere, then 1 at local index j of every cut cell
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_dofs; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) unit_rows_set_kernel(int nd, int n_cut, const int32_t* __restrict__ cut_rank,
+                                                            int j, T* __restrict__ x) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cut; c += gridDim.x * blockDim.x)
+    x[(int64_t)cut_rank[c] * nd + j] = T(1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) matrix_column_kernel(int nd, int n_cut, const int32_t* __restrict__ cut_rank,
+                                                            int j, const T* __restrict__ v, T* __restrict__ mat) {
+  const int64_t total = (int64_t)n_cut * nd;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = idx / nd;
+    const int i = (int)(idx % nd);
+    mat[c * nd * (int64_t)nd + (int64_t)j * nd + i] = v[(int64_t)cut_rank[c] * nd + i];
+  }
+}
+
+__global__ void __launch_bounds__(256) matrix_cast_kernel(int64_t n, const double* __restrict__ in,
+                                                          float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+int grid_for2(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+hipError_t launch_unit_rows(int prec, int64_t n_dofs, int nd, int n_cut, const int32_t* cut_rank, int j, void* x,
+                            hipStream_t s) {
+  if (prec == 0) {
+    unit_rows_kernel<double><<<grid_for2(n_dofs), 256, 0, s>>>(n_dofs, nd, n_cut, cut_rank, j, (double*)x);
+    if (n_cut > 0) unit_rows_set_kernel<double><<<grid_for2(n_cut), 256, 0, s>>>(nd, n_cut, cut_rank, j, (double*)x);
+  } else {
+    unit_rows_kernel<float><<<grid_for2(n_dofs), 256, 0, s>>>(n_dofs, nd, n_cut, cut_rank, j, (float*)x);
+    if (n_cut > 0) unit_rows_set_kernel<float><<<grid_for2(n_cut), 256, 0, s>>>(nd, n_cut, cut_rank, j, (float*)x);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_matrix_column(int prec, int nd, int n_cut, const int32_t* cut_rank, int j, const void* v, void* mat,
+                                hipStream_t s) {
+  if (n_cut <= 0) return hipSuccess;
+  const int g = grid_for2((int64_t)n_cut * nd);
+  if (prec == 0)
+    matrix_column_kernel<double><<<g, 256, 0, s>>>(nd, n_cut, cut_rank, j, (const double*)v, (double*)mat);
+  else
+    matrix_column_kernel<float><<<g, 256, 0, s>>>(nd, n_cut, cut_rank, j, (const float*)v, (float*)mat);
+  return hipGetLastError();
+}
+
+hipError_t launch_matrix_cast(int64_t n, const double* in, float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  matrix_cast_kernel<<<grid_for2(n), 256, 0, s>>>(n, in, out);
+  return hipGetLastError();
+}
+
+}  // namespace ufem

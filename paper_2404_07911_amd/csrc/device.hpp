@@ -30,7 +30,9 @@ constexpr int kFlagNoVolume = 24;
 //   GP[4*K*K] face ghost penalty of a face on side s (0: lower, 1: upper) of
 //             the own cell, GP[(2s+n)*K*K + l*K + m] = sum_j gamma_j E^j_l
 //             F^j_m with E the own basis derivatives at the face and F = E
-//             (n = 0) or the neighbour's (n = 1)
+//             (n = 0) or the neighbour's (n = 1); with the volume ghost
+//             penalty tau_v times the 1D mass of the own basis with the own
+//             (n = 0) or the neighbour's (n = 1) basis over the two-cell patch
 // (kernels that stage the table in LDS copy its first lds_size(K) entries)
 // Line batches of the cut-cell kernels.  Batch b has a record of
 // batch_record_ints(ME) ints at a fixed stride: (entries, lines, offset of
@@ -56,6 +58,7 @@ constexpr __host__ __device__ int batch_max_cells(int nd, bool face) {
 }
 constexpr __host__ __device__ int batch_record_ints(int me) { return 4 + 4 * me; }
 constexpr int kBatchLines = 64;        // lines per round (one per lane)
+
 constexpr int kBatchOffsetBits = 24;   // bits of the in-batch line offset
 
 struct TabOff {
@@ -110,6 +113,10 @@ struct DevArgs {
   int64_t n_vol, n_surf, n_fcut;
   int64_t seg[6];
   const T* tab;
+  // mixed evaluation: element matrices of the cut cells' volume and interface
+  // terms (cut order, column-major nd x nd), nullptr: matrix-free
+  const T* cmat;
+  const int32_t* cut_rank;   // active rank of each cut cell (cut order)
   const T* kappa;            // nullptr: kappa = 1
   T hs;                      // h^(dim - 2)
   T tau, gamma;
@@ -117,6 +124,8 @@ struct DevArgs {
   int32_t parts;             // stage bits: 1 inside cells, 2 structured faces and ghost
                              // penalty of the cut cells, 4 cut volume and interface
                              // lines, 8 cut-face lines
+  int32_t gp_volume;         // the ghost penalty is the volume kind (GP tables
+                             // hold tau_v times the patch mass matrices)
   int32_t max_blocks;        // > 0: cap on the workgroups of every launch (the
                              // grid-stride and persistent loops then take
                              // several cell groups / batches per workgroup)
@@ -134,6 +143,14 @@ hipError_t launch_operator(const DevArgs<T>& a, int dim, int degree, const T* u,
 
 hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const void* ap, double* scal,
                            hipStream_t s);
+
+// Mixed evaluation set-up (blas.hip): x := e_j in the rows of the cut cells
+// (0 elsewhere); column j of the element matrices from the stage-4 result v.
+hipError_t launch_unit_rows(int prec, int64_t n_dofs, int nd, int n_cut, const int32_t* cut_rank, int j, void* x,
+                            hipStream_t s);
+hipError_t launch_matrix_column(int prec, int nd, int n_cut, const int32_t* cut_rank, int j, const void* v, void* mat,
+                                hipStream_t s);
+hipError_t launch_matrix_cast(int64_t n, const double* in, float* out, hipStream_t s);
 // Static workspace of ufem_cg_iterate_static (blas.hip): 64 MiB for A p after
 // 256 bytes of CG scalars.  static_scratch_address gives the calling
 // thread's current device's copy.

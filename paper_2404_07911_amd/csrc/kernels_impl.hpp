@@ -131,9 +131,15 @@ template <int K, int D, typename T>
 struct KronWork {
   static constexpr int NDP = KronLayout<K, D>::NDP, C = KronShape<K, D>::C;
   T A[C][NDP];
-  T B[C][NDP];
   T Cc[C][NDP];
   T U[C][NDP];
+};
+
+// waves per SIMD the Kronecker kernel asks the compiler for (the register
+// budget 512 / W): K = 4 in double at 5, where its three LDS tensors allow it
+template <int K, typename T>
+struct KronOcc {
+  static constexpr int W = 1;
 };
 
 template <int K, typename T>
@@ -208,8 +214,10 @@ __device__ __forceinline__ void line_faces(const T* __restrict__ tab, const DevA
       for (int l = 0; l < K; ++l) R[l] += Eo[l] * cv + Eo[K + l] * cd;
     }
     if (fg) {
-      // sum_j gamma_j E^j_l (d^j u_own - d^j u_nb), folded into two K x K
-      // matrices on the host
+      // face ghost penalty: sum_j gamma_j E^j_l (d^j u_own - d^j u_nb),
+      // folded into two K x K matrices on the host; volume ghost penalty:
+      // tau_v times the patch mass products along the line (the in-face
+      // mass follows in the later passes)
       const T* Go = tab + TabOff::GP(K) + 2 * side * K * K;
       const T* Gn = Go + K * K;
 #pragma unroll
@@ -237,7 +245,7 @@ __device__ __forceinline__ void glb_line_load(const T* __restrict__ src, int bas
 // K^2 FMAs and K stores per lane and the 1D matrices are wave-uniform:
 //   v = hs [ M_z (M_y R_x + M_x R_y) + M_y M_x R_z ]
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KronOcc<K, T>::W))) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                          const int32_t* __restrict__ kinfo, int n_list, int with_volume) {
   constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
   __shared__ KronWork<K, D, T> W;
@@ -281,13 +289,14 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
     }
     T* U = W.U[active ? c : 0];
     T* A = W.A[active ? c : 0];
-    T* B = W.B[active ? c : 0];
     T* Cc = W.Cc[active ? c : 0];
     T t0[K], t1[K], t2[K];
     int px[K], py[K], pz[K];
     KronLayout<K, D>::template line<0>(l, px);
     KronLayout<K, D>::template line<1>(l, py);
     if constexpr (D == 3) KronLayout<K, D>::template line<2>(l, pz);
+    // Three cell tensors in LDS (A, Cc, U); each pass reads and writes only
+    // its own lanes' lines, so the updates in place need no extra array.
     // pass x1: R_x = KS u + x-faces -> A ; u -> U
     if (valid) {
       kl_store<K>(U, px, ux);
@@ -300,33 +309,23 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
       kl_store<K>(A, px, t0);
     }
     sync();
+    // pass y1: R_y = KS u + y-faces -> Cc ; A = M_y R_x (in place)
+    if (valid) {
+      kl_load<K>(U, py, t1);
+      if (vol) line_mat<K>(KS, t1, t0);
+      else {
+#pragma unroll
+        for (int q = 0; q < K; ++q) t0[q] = 0;
+      }
+      line_faces<K>(tab, a, fl, 1, t1, nb[2], nb[3], t0);
+      kl_store<K>(Cc, py, t0);
+      kl_load<K>(A, py, t1);
+      line_mat<K>(M, t1, t2);
+      kl_store<K>(A, py, t2);
+    }
+    sync();
     if constexpr (D == 3) {
-      // pass y1: R_y = KS u + y-faces -> Cc ; P = M_y R_x -> B
-      if (valid) {
-        kl_load<K>(U, py, t1);
-        if (vol) line_mat<K>(KS, t1, t0);
-        else {
-#pragma unroll
-          for (int q = 0; q < K; ++q) t0[q] = 0;
-        }
-        line_faces<K>(tab, a, fl, 1, t1, nb[2], nb[3], t0);
-        kl_store<K>(Cc, py, t0);
-        kl_load<K>(A, py, t1);
-        line_mat<K>(M, t1, t2);
-        kl_store<K>(B, py, t2);
-      }
-      sync();
-      // pass x2: S = P + M_x R_y -> A
-      if (valid) {
-        kl_load<K>(Cc, px, t1);
-        line_mat<K>(M, t1, t2);
-        kl_load<K>(B, px, t1);
-#pragma unroll
-        for (int q = 0; q < K; ++q) t2[q] += t1[q];
-        kl_store<K>(A, px, t2);
-      }
-      sync();
-      // pass z1: R_z = KS u + z-faces -> Cc ; O = M_z S -> B
+      // pass z1: R_z = KS u + z-faces -> U (in place)
       if (valid) {
         kl_load<K>(U, pz, t1);
         if (vol) line_mat<K>(KS, t1, t0);
@@ -335,49 +334,44 @@ __global__ void __launch_bounds__(64) inside_kron_kernel(DevArgs<T> a, const T* 
           for (int q = 0; q < K; ++q) t0[q] = 0;
         }
         line_faces<K>(tab, a, fl, 2, t1, nb[4], nb[5], t0);
-        kl_store<K>(Cc, pz, t0);
-        kl_load<K>(A, pz, t1);
-        line_mat<K>(M, t1, t2);
-        kl_store<K>(B, pz, t2);
+        kl_store<K>(U, pz, t0);
       }
       sync();
-      // pass x3: V = M_x R_z -> A
+      // pass x2: S = M_y R_x + M_x R_y -> A ; M_x R_z -> Cc
       if (valid) {
         kl_load<K>(Cc, px, t1);
         line_mat<K>(M, t1, t2);
+        kl_load<K>(A, px, t1);
+#pragma unroll
+        for (int q = 0; q < K; ++q) t2[q] += t1[q];
         kl_store<K>(A, px, t2);
+        kl_load<K>(U, px, t1);
+        line_mat<K>(M, t1, t2);
+        kl_store<K>(Cc, px, t2);
       }
       sync();
-      // pass y2: v = hs (M_y V + O)
+      // pass z2: M_z S -> U
       if (valid) {
-        kl_load<K>(A, py, t1);
+        kl_load<K>(A, pz, t1);
         line_mat<K>(M, t1, t2);
-        kl_load<K>(B, py, t1);
+        kl_store<K>(U, pz, t2);
+      }
+      sync();
+      // pass y2: v = hs (M_z S + M_y M_x R_z)
+      if (valid) {
+        kl_load<K>(Cc, py, t1);
+        line_mat<K>(M, t1, t2);
+        kl_load<K>(U, py, t1);
         T* out = v + (int64_t)r * ND;
 #pragma unroll
         for (int q = 0; q < K; ++q) out[by + q * K] = a.hs * (t2[q] + t1[q]);
       }
     } else {
-      // pass y1: R_y = KS u + y-faces -> Cc ; P = M_y R_x -> B
-      if (valid) {
-        kl_load<K>(U, py, t1);
-        if (vol) line_mat<K>(KS, t1, t0);
-        else {
-#pragma unroll
-          for (int q = 0; q < K; ++q) t0[q] = 0;
-        }
-        line_faces<K>(tab, a, fl, 1, t1, nb[2], nb[3], t0);
-        kl_store<K>(Cc, py, t0);
-        kl_load<K>(A, py, t1);
-        line_mat<K>(M, t1, t2);
-        kl_store<K>(B, py, t2);
-      }
-      sync();
-      // pass x2: v = hs (P + M_x R_y)
+      // pass x2: v = hs (M_y R_x + M_x R_y)
       if (valid) {
         kl_load<K>(Cc, px, t1);
         line_mat<K>(M, t1, t2);
-        kl_load<K>(B, px, t1);
+        kl_load<K>(A, px, t1);
         T* out = v + (int64_t)r * ND;
 #pragma unroll
         for (int q = 0; q < K; ++q) out[bx + q] = a.hs * (t2[q] + t1[q]);
@@ -687,12 +681,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 
         // ghost penalty: derivative jumps of every order, exact in-face mass
         // (skipped by waves without such a face on this slot)
         if (__any(fg)) {
+          // face kind: the jumps of the normal derivatives of every order,
+          // FJ[j] = E^j u_own - F^j u_nb; volume kind: the line of the patch
+          // mass products, FJ[j] = (Go u_own - Gn u_nb)[j] (the in-face mass
+          // of the patch integral is the face transform below)
+          const T* Go = tab + TabOff::GP(K) + 2 * side * K * K;
+          const T* Gn = Go + K * K;
+          const bool vgp = a.gp_volume != 0;
           if (fg) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
               T dj = 0;
 #pragma unroll
-              for (int q = 0; q < K; ++q) dj += Eo[j * K + q] * uo[q] - En[j * K + q] * un[q];
+              for (int q = 0; q < K; ++q)
+                dj += vgp ? Go[j * K + q] * uo[q] - Gn[j * K + q] * un[q] : Eo[j * K + q] * uo[q] - En[j * K + q] * un[q];
               W.FJ[cc][j][l] = dj;
             }
           }
@@ -700,9 +702,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 
           if (fg) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-              const T g = a.hs * GW[j] * face_transform<K, D, false>(M, W.FJ[cc][j], l);
+              const T g = a.hs * face_transform<K, D, false>(M, W.FJ[cc][j], l);
+              if (vgp) {
+                R[j] += g;
+              } else {
 #pragma unroll
-              for (int q = 0; q < K; ++q) R[q] += Eo[j * K + q] * g;
+                for (int q = 0; q < K; ++q) R[q] += Eo[j * K + q] * (GW[j] * g);
+              }
             }
           }
           sync();
@@ -2081,6 +2087,44 @@ cut_face_dk_kernel(DevArgs<T> a, const T* __restrict__ w,
   }
 }
 
+// ------------------------------------------------ mixed evaluation
+// The cut cells' volume and interface terms as precomputed element matrices
+// (the "mixed" option of Section 3.2, eq. additive_decomp: the unstructured
+// cell integrals precomputed, the rest matrix-free).  One wave per cut cell
+// and round of 64 rows; the matrix is column-major, so that the lanes' row
+// entries of one column are contiguous; the cell's DoFs come from LDS.  The
+// product is added to v (stage 4).  A streaming kernel: nd^2 values per
+// cell against 2 nd flops each row, far below any ridge point.
+template <int K, int D, typename T>
+__global__ void __launch_bounds__(64) cut_matrix_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v) {
+  constexpr int ND = ipow(K, D), NPL = (ND + 63) / 64;
+  __shared__ T U[ND];
+  const int t = threadIdx.x;
+  for (int c = blockIdx.x; c < a.n_cut; c += gridDim.x) {
+    const int64_t r = a.cut_rank[c];
+    for (int i = t; i < ND; i += 64) U[i] = x[r * ND + i];
+    sync();
+    const T* M = a.cmat + (int64_t)c * ND * ND;
+    T acc[NPL];
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) acc[j] = 0;
+    for (int col = 0; col < ND; ++col) {
+      const T uc = U[col];
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        const int i = t + 64 * j;
+        if (i < ND) acc[j] += M[(int64_t)col * ND + i] * uc;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) {
+      const int i = t + 64 * j;
+      if (i < ND) v[r * ND + i] += acc[j];
+    }
+    sync();
+  }
+}
+
 // resident workgroups of a kernel per compute unit (persistent grids)
 template <typename Kern>
 int blocks_per_cu(Kern kernel) {
@@ -2150,7 +2194,9 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
         kappa_struct_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.kface_cut, a.n_cut,
                                                                         0);
     }
-    if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
+    if ((a.parts & 4) && a.cmat != nullptr && a.n_cut > 0) {
+      cut_matrix_kernel<K, D, T><<<grid_cap(a, a.n_cut), 64, 0, s>>>(a, x, v);
+    } else if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
       static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
       const int g = grid_cap(a, std::min(a.n_vbatch, nb * a.n_cu));
       cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);

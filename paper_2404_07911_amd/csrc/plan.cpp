@@ -659,6 +659,36 @@ std::string finish_rules(Plan& P, int* code) {
     P.face_line_off[i + 1] = (int64_t)P.line_first.size();
   }
 
+  // -- volume ghost penalty with stable neighbours: the faces of the patches
+  // (each cut cell with the face neighbour of largest volume fraction; a
+  // later slot wins only by more than 1e-10)
+  if (P.gp_kind == UFEM_GP_VOLUME) {
+    std::vector<double> frac(P.active.size(), 1.0);
+    for (size_t i = 0; i < ncut; ++i) {
+      double s = 0.0;
+      for (int64_t q = P.vol_off[i]; q < P.vol_off[i + 1]; ++q) s += P.vol_w[q];
+      frac[P.cut[i]] = s;
+    }
+    for (Face& f : P.faces) f.gp = 0;
+    const int S = 2 * dim;
+    for (size_t i = 0; i < ncut; ++i) {
+      const int32_t r = P.cut[i];
+      int32_t best_fi = -1;
+      double best_f = 0.0;
+      for (int sl = 0; sl < S; ++sl) {
+        const int32_t fi = P.slot_face[(size_t)r * S + sl];
+        if (fi < 0) continue;
+        const Face& f = P.faces[fi];
+        const int32_t nb = P.rank[(sl & 1) ? f.bp : f.bm];
+        if (best_fi < 0 || frac[nb] > best_f + 1e-10) {
+          best_fi = fi;
+          best_f = frac[nb];
+        }
+      }
+      if (best_fi >= 0) P.faces[best_fi].gp = 1;
+    }
+  }
+
   // -- kappa layout
   const int nd = P.nd(), nf = P.nf();
   P.seg[0] = 0;
@@ -700,6 +730,8 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
     return "need at least one ball (centers, radii)";
   if (pr.q_cut < 0 || pr.q_cut > 16) return "q_cut must be in [0, 16]";
   if (pr.gp_jmin < 0 || pr.gp_jmin > pr.degree + 1) return "gp_jmin out of range";
+  if (pr.gp_kind != UFEM_GP_FACE && pr.gp_kind != UFEM_GP_VOLUME && pr.gp_kind != UFEM_GP_VOLUME_ALL)
+    return "unknown ghost-penalty kind";
   double cells = std::pow((double)pr.n, pr.dim);
   if (cells > 2.2e9) return "background mesh too large";
   P.prob = pr;
@@ -730,6 +762,7 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
   }
   P.prob.centers = nullptr;
   P.prob.radii = nullptr;
+  P.gp_kind = pr.gp_kind;
   P.tau = pr.nitsche_factor * P.p * P.p;
   P.gamma = pr.sipg_factor * P.p * P.p;
   P.gp_w.assign(P.p + 1, 0.0);

@@ -31,6 +31,7 @@ struct Plan {
   int dim = 3, n = 0, p = 1, k = 2, q = 2, max_depth = 4;
   double h = 0.0, lo = 0.0;
   double tau = 0.0, gamma = 0.0;
+  int gp_kind = UFEM_GP_FACE;      // ghost-penalty kind (ufem.h)
   std::vector<double> gp_w;  // gamma_j for j = 0..p (0 below jmin)
 
   std::vector<int8_t> cls;      // per background cell

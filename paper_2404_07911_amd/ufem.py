@@ -34,6 +34,7 @@ class Problem:
     gp_jmin: int = 0
     gp_flat: bool = False
     plane: tuple | None = None
+    gp_kind: str = "face"  # "face", "volume" (stable neighbours) or "volume_all"
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -59,6 +60,10 @@ class Problem:
         s.gp_gamma = self.gp_gamma
         s.gp_jmin = self.gp_jmin
         s.gp_flat = int(bool(self.gp_flat))
+        kinds = {"face": L.GP_FACE, "volume": L.GP_VOLUME, "volume_all": L.GP_VOLUME_ALL}
+        if self.gp_kind not in kinds:
+            raise ValueError(f"gp_kind must be one of {sorted(kinds)}")
+        s.gp_kind = kinds[self.gp_kind]
         if self.plane is not None:
             nrm = np.asarray(self.plane[0], dtype=np.float64).reshape(-1)
             s.levelset = L.LEVELSET_PLANE
@@ -203,6 +208,11 @@ class Operator:
     def set_terms(self, mask: int):
         L.check(L.lib().ufem_set_terms(self._h, int(mask)))
         self.terms = int(mask)
+
+    def set_mixed(self, enable: bool, stream=None):
+        """Precomputed element matrices for the cut cells' volume and
+        interface terms (True) or fully matrix-free evaluation (False)."""
+        L.check(L.lib().ufem_set_mixed(self._h, int(bool(enable)), _stream_handle(stream)))
 
     def set_max_blocks(self, max_blocks: int):
         """Cap the workgroups of every launch (0: sized by the work)."""

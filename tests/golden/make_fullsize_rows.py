@@ -7,7 +7,8 @@ whole mesh in the benchmark's launch configuration and compare the rows of
 the sampled cells with the values stored here.
 
 Usage:  python tests/golden/make_fullsize_rows.py [name ...]
-        (names: balls3d, kappa3d, sweep1 ... sweep7; default all)
+        (names: ball3d, balls3d, kappa3d, sweep1 ... sweep7, plane_p<p>_l<layer>;
+        default all)
 
 Per workload the file fullsize_<name>.npz holds
   cells      sampled active cells (background indices): random inside and cut
@@ -18,7 +19,7 @@ Per workload the file fullsize_<name>.npz holds
   rows32     v = A u32 (u rounded to float32, evaluated in float64)
   rows_adj   A^T w = A w on those rows (kappa of the workload)
   dk_idx, dk_val   dL/dkappa at every quadrature point of the sampled cells
-             and of the faces touching them (kappa workload only)
+             and of the faces touching them (ball and kappa workloads)
 Draw order as everywhere: geometry, u, then w.
 """
 from __future__ import annotations
@@ -40,26 +41,31 @@ from oracle.operator import ALL, UnfittedDG  # noqa: E402
 
 
 def workload(name):
+    if name == "ball3d":
+        return ui.ball3d(0)
     if name == "balls3d":
         return ui.balls3d(0)
     if name == "kappa3d":
         return ui.kappa3d(0)
     if name.startswith("sweep"):
         return ui.sweep3d(int(name[5:]), 0)
+    if name.startswith("plane_p"):
+        p, layer = name[7:].split("_l")
+        return ui.plane3d(int(layer), 0, n=128, degree=int(p))
     raise ValueError(name)
 
 
 def make(name, n_inside=4, n_cut=8):
     t0 = time.time()
     wl, rng = workload(name)
-    ora = UnfittedDG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi)
+    ora = UnfittedDG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi, plane=wl.plane)
     print(f"[{name}] oracle built in {time.time() - t0:.0f} s, {ora.n_dofs} DoF", flush=True)
     u = ui.uniform_vector(rng, ora.n_dofs)
     w = ui.uniform_vector(rng, ora.n_dofs)
     pick = np.random.default_rng(7)
-    cells = [int(b) for b in pick.choice(ora.inside_cells, n_inside, replace=False)]
+    cells = [int(b) for b in pick.choice(ora.inside_cells, min(n_inside, len(ora.inside_cells)), replace=False)]
     cells += [int(b) for b in pick.choice(ora.cut_cells, n_cut, replace=False)]
-    with_layout = name in ("balls3d", "kappa3d")
+    with_layout = name in ("ball3d", "balls3d", "kappa3d")
     kap = None
     if with_layout:
         L = ora.layout()
@@ -78,7 +84,7 @@ def make(name, n_inside=4, n_cut=8):
     u32 = u.astype(np.float32).astype(np.float64)
     out["rows32"] = rows(ora.apply(u32, ALL, kap, cells=cells))
     out["rows_adj"] = rows(ora.apply(w, ALL, kap, cells=cells))
-    if name == "kappa3d":
+    if name in ("ball3d", "kappa3d"):
         dk = ora.dkappa(w, u, cells=cells)
         idx = []
         for b in cells:
@@ -100,7 +106,8 @@ def make(name, n_inside=4, n_cut=8):
 
 
 def main(argv):
-    names = argv or ["kappa3d", "balls3d"] + [f"sweep{p}" for p in range(1, 8)]
+    names = argv or (["ball3d", "kappa3d", "balls3d"] + [f"sweep{p}" for p in range(1, 8)]
+                     + ["plane_p1_l0", "plane_p1_l9", "plane_p3_l0", "plane_p3_l1"])
     for nm in names:
         make(nm)
 

@@ -75,12 +75,22 @@ SMALL_CASES = {
     "plane3d_p2": (ui.plane, dict(dim=3, n=8, degree=2, normal=[0.3, -0.5, 0.81], offset=0.07, seed=25)),
     "plane2d_p3": (ui.plane, dict(dim=2, n=10, degree=3, normal=[0.6, -0.8], offset=0.05, seed=26)),
     "plane3d_layer_p1": (ui.plane3d, dict(layer=3, n=12, degree=1, seed=27)),
+    # the volume ghost penalty (Section 2.2): stable-neighbour patches, and
+    # every face of a cut cell (all-neighbours strategy)
+    "ball3d_p2_vgp": (ui.ball3d, dict(seed=8, n=10, degree=2)),
+    "ball3d_p3_vgp": (ui.ball3d, dict(seed=9, n=8, degree=3)),
+    "disk2d_p3_vgp": (ui.disk2d, dict(seed=10, n=12, degree=3)),
+    "balls3d_p2_vgp_all": (ui.balls3d, dict(seed=11, n=12, degree=2, n_balls=4)),
 }
 
 # options of the plan and of the oracle beyond the workload (same keywords)
 CASE_OPTIONS = {
     "union2d_fallback": dict(max_depth=0),
     "union3d_fallback": dict(max_depth=0),
+    "ball3d_p2_vgp": dict(gp_kind="volume"),
+    "ball3d_p3_vgp": dict(gp_kind="volume"),
+    "disk2d_p3_vgp": dict(gp_kind="volume"),
+    "balls3d_p2_vgp_all": dict(gp_kind="volume_all"),
 }
 
 

@@ -203,25 +203,33 @@ def test_full_size_ball_sampled_rows(torch):
 
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-FULL = ["balls3d", "kappa3d"] + [f"sweep{p}" for p in range(1, 8)]
+FULL = (["ball3d", "balls3d", "kappa3d"] + [f"sweep{p}" for p in range(1, 8)]
+        + ["plane_p1_l0", "plane_p1_l9", "plane_p3_l0", "plane_p3_l1"])
 
 
 def _full_workload(name):
+    if name == "ball3d":
+        return ui.ball3d(0)
     if name == "balls3d":
         return ui.balls3d(0)
     if name == "kappa3d":
         return ui.kappa3d(0)
+    if name.startswith("plane_p"):
+        p, layer = name[7:].split("_l")
+        return ui.plane3d(int(layer), 0, n=128, degree=int(p))
     return ui.sweep3d(int(name[5:]), 0)
 
 
 @pytest.mark.parametrize("name", FULL)
 def test_full_size_sampled_rows_against_stored_oracle_rows(torch, name):
-    """The full workloads (20 balls at 128^3, p = 3; the kappa field at 48^3,
-    p = 4; the degree sweep at about 2e7 active DoF, p = 1..7) in the
-    benchmark's launch configuration: FP64 and FP32 applies, the adjoint pass
-    and, with the kappa field, dL/dkappa, on the rows / points of sampled
-    cells, against oracle values written by tests/golden/make_fullsize_rows.py
-    for the same seeded inputs."""
+    """The full workloads (the ball at 64^3, p = 3; 20 balls at 128^3, p = 3;
+    the kappa field at 48^3, p = 4; the degree sweep at about 2e7 active DoF,
+    p = 1..7; the plane benchmark at 128^3, p = 1 and 3, cut-cell ratios 1,
+    0.5 and 0.1) in the benchmark's launch configuration: FP64 and FP32
+    applies, the adjoint pass and, for the ball and the kappa field,
+    dL/dkappa, on the rows / points of sampled cells, against oracle values
+    written by tests/golden/make_fullsize_rows.py for the same seeded
+    inputs."""
     from paper_2404_07911_amd import Operator, Plan, Problem
 
     ref = np.load(os.path.join(GOLDEN, f"fullsize_{name}.npz"))
@@ -367,3 +375,38 @@ def test_apply_with_imported_oracle_quadrature(torch, name):
     atw, dk = op.apply_adjoint(torch.from_numpy(w).cuda(), ud)
     assert _rel(atw.cpu().numpy(), ora.apply(w, ALL, kap)) < TOL64
     assert _rel(dk.cpu().numpy(), ora.dkappa(w, u)) < TOL64
+
+
+@pytest.mark.parametrize("name", ["ball3d_p1", "ball3d_p3", "disk2d_p2", "balls3d_p2", "plane3d_p2",
+                                  "union3d_fallback", "ball3d_p2_vgp", "disk2d_p7"])
+def test_mixed_evaluation(torch, name):
+    """The mixed evaluation (the cut cells' volume and interface terms as
+    precomputed element matrices, the rest matrix-free) against the oracle:
+    FP64 and FP32 applies per term and whole, and the adjoint pass with a
+    kappa field (the matrices follow set_terms and set_kappa); back to the
+    matrix-free evaluation afterwards."""
+    from paper_2404_07911_amd import TERM_ALL
+
+    wl, ora, pl, op, u, w = _setup(name)
+    ud = torch.from_numpy(u).cuda()
+    free = op.apply(ud).clone()
+    try:
+        _say(f"[{name}] mixed")
+        op.set_mixed(True)
+        for mask in (VOL, NITSCHE, ALL):
+            op.set_terms(mask)
+            assert _rel(op.apply(ud).cpu().numpy(), ora.apply(u, mask)) < TOL64, mask
+        op.set_terms(TERM_ALL)
+        u32 = u.astype(np.float32)
+        v32 = op.apply(torch.from_numpy(u32).cuda()).cpu().numpy().astype(np.float64)
+        assert _rel(v32, ora.apply(u32.astype(np.float64))) < TOL32
+        kap = ui.kappa_field(ora.qp_physical_points())
+        op.set_kappa(torch.from_numpy(kap).cuda())
+        atw, dk = op.apply_adjoint(torch.from_numpy(w).cuda(), ud)
+        assert _rel(atw.cpu().numpy(), ora.apply(w, ALL, kap)) < TOL64
+        assert _rel(dk.cpu().numpy(), ora.dkappa(w, u)) < TOL64
+    finally:
+        op.set_mixed(False)
+        op.set_terms(TERM_ALL)
+        op.set_kappa(None)
+    assert torch.equal(op.apply(ud), free)
