@@ -96,6 +96,18 @@ enum { UFEM_LEVELSET_BALLS = 0, UFEM_LEVELSET_PLANE = 1 };
  * VOLUME_ALL: the same term on every face of a cut cell. */
 enum { UFEM_GP_FACE = 0, UFEM_GP_VOLUME = 1, UFEM_GP_VOLUME_ALL = 2 };
 
+/* Function spaces of ufem_problem.space.  DG: the discontinuous Q_p space
+ * with the SIPG interior-face terms (eq. bilinear_dg).  CG: the continuous
+ * Q_p space (FE_Q, eq. bilinear_cg: Poisson and Nitsche terms, no SIPG)
+ * with the same ghost penalty; its DoFs are the Gauss-Lobatto nodes of the
+ * active cells on the global node lattice ((n p + 1)^dim nodes, node
+ * (I_0, I_1, I_2) at lo + h (I / p)), numbered in lattice order (I_0
+ * fastest).  The operator is evaluated as P^T A_cell P with P the copy of
+ * node values into the cells' DoFs and P^T the sum of the cells'
+ * contributions per node (the read and distribute operators R, D of Section
+ * 3.1, eq. matrixfreeopcompact). */
+enum { UFEM_SPACE_DG = 0, UFEM_SPACE_CG = 1 };
+
 /* Problem description.  All pointers are host pointers read during
  * ufem_plan_create only.  The physical domain is {phi < 0}. */
 typedef struct {
@@ -120,6 +132,7 @@ typedef struct {
   double plane_offset;   /* PLANE: offset; phi = (n . x - offset) / |n| */
   int32_t gp_kind;       /* UFEM_GP_FACE (0, default), UFEM_GP_VOLUME or
                             UFEM_GP_VOLUME_ALL */
+  int32_t space;         /* UFEM_SPACE_DG (0, default) or UFEM_SPACE_CG */
 } ufem_problem;
 
 typedef struct {
@@ -127,7 +140,8 @@ typedef struct {
   int64_t n_active;     /* cells with DoFs: inside + cut */
   int64_t n_inside;
   int64_t n_cut;
-  int64_t n_dofs;       /* n_active * (p+1)^dim */
+  int64_t n_dofs;       /* DoFs of the space: n_active * (p+1)^dim (DG), the
+                           nodes of the active cells (CG) */
   int64_t n_faces;      /* interior faces between active cells */
   int64_t n_faces_str;  /* with structured SIPG quadrature */
   int64_t n_faces_cut;  /* with dimension-reduction SIPG quadrature */
@@ -137,6 +151,7 @@ typedef struct {
   int64_t max_qp_cut_cell; /* largest cut-cell volume rule */
   int64_t n_fallback;   /* sub-boxes that hit the subdivision limit */
   double h;             /* background cell size */
+  int64_t n_cell_dofs;  /* n_active * (p+1)^dim (equal to n_dofs for DG) */
 } ufem_info;
 
 /* Build the host plan: cell classes (inside / cut / outside by exact

@@ -519,3 +519,74 @@ class UnfittedDG:
 
 def from_workload(wl, **kw):
     return UnfittedDG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi, **kw)
+
+
+class UnfittedCG:
+    """The continuous Q_p space (FE_Q) on the same mesh, level set and
+    quadrature (Section 2.1, eq. bilinear_cg: Poisson and Nitsche terms; the
+    ghost penalty as for DG; no interior-face term).
+
+    DoFs are the Gauss-Lobatto nodes of the active cells on the global node
+    lattice ((n p + 1)^d nodes, node (I_0, .., I_{d-1}) at lo + h I / p),
+    numbered in lattice order (I_0 fastest).  A continuous function is the
+    same polynomial on both sides of every face, so its cell DoFs are its
+    node values copied into each cell (u_cell = P u), and the form, being a
+    sum of cell, interface and face integrals, is
+
+        A_CG = P^T A_cell P,
+
+    A_cell the cell-DoF operator of UnfittedDG without the SIPG term (which
+    vanishes on continuous test and trial functions anyway).
+    """
+
+    def __init__(self, *args, **kw):
+        self.dg = UnfittedDG(*args, **kw)
+        dg = self.dg
+        self.dim, self.p, self.k, self.nd, self.h = dg.dim, dg.p, dg.k, dg.nd, dg.h
+        L1 = dg.mesh.n * dg.p + 1
+        lat = np.zeros((dg.active.size, dg.nd), dtype=np.int64)
+        for r, b in enumerate(dg.active):
+            ijk = dg.mesh.index_to_ijk(int(b))
+            for l in range(dg.nd):
+                g, stride, rem = 0, 1, l
+                for a in range(dg.dim):
+                    g += (ijk[a] * dg.p + rem % dg.k) * stride
+                    rem //= dg.k
+                    stride *= L1
+                lat[r, l] = g
+        self.lattice = np.unique(lat)  # active nodes in lattice order
+        self.cell_node = np.searchsorted(self.lattice, lat.reshape(-1))
+        self.n_dofs = self.lattice.size
+        self.L1 = L1
+
+    def gather(self, u):
+        """P u: node values into the cells' DoFs."""
+        return np.asarray(u, dtype=np.float64)[self.cell_node]
+
+    def scatter(self, v_cell):
+        """P^T v: each node sums its cells' values."""
+        return np.bincount(self.cell_node, weights=v_cell, minlength=self.n_dofs)
+
+    def apply(self, u, mask=ALL, kappa=None):
+        return self.scatter(self.dg.apply(self.gather(u), mask & ~SIPG, kappa))
+
+    def dkappa(self, w, u):
+        """dL/dkappa_q of the continuous operator (the SIPG points of the
+        kappa layout carry no term: 0)."""
+        return self.dg._evaluate(self.gather(w), self.gather(u), ALL & ~SIPG, None, None, want_dkappa=True)[1]
+
+    def node_points(self):
+        """Physical coordinates of the nodes."""
+        nodes = gauss_lobatto_nodes(self.k)
+        X = np.zeros((self.n_dofs, self.dim))
+        rem = self.lattice.copy()
+        for a in range(self.dim):
+            I = rem % self.L1
+            rem //= self.L1
+            c, i = np.divmod(I, self.p)
+            # the last node of the lattice belongs to the last cell's end
+            X[:, a] = self.dg.mesh.lo + self.h * (c + nodes[i])
+        return X
+
+    def dof_values_of(self, fn):
+        return np.array([fn(x) for x in self.node_points()])

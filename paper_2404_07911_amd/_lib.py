@@ -12,6 +12,7 @@ TERM_VOLUME, TERM_SIPG, TERM_NITSCHE, TERM_GHOST, TERM_ALL = 1, 2, 4, 8, 15
 F64, F32 = 0, 1
 LEVELSET_BALLS, LEVELSET_PLANE = 0, 1
 GP_FACE, GP_VOLUME, GP_VOLUME_ALL = 0, 1, 2
+SPACE_DG, SPACE_CG = 0, 1
 PART_INSIDE, PART_CUT_STRUCTURED, PART_CUT_LINES, PART_CUT_FACE_LINES = 1, 2, 4, 8
 PART_CUT, PART_ALL = 14, 15
 
@@ -37,6 +38,7 @@ class ufem_problem(C.Structure):
         ("plane_normal", C.c_double * 3),
         ("plane_offset", C.c_double),
         ("gp_kind", C.c_int32),
+        ("space", C.c_int32),
     ]
 
 
@@ -56,6 +58,7 @@ class ufem_info(C.Structure):
         ("max_qp_cut_cell", C.c_int64),
         ("n_fallback", C.c_int64),
         ("h", C.c_double),
+        ("n_cell_dofs", C.c_int64),
     ]
 
     def as_dict(self):

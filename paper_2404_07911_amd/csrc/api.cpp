@@ -76,7 +76,8 @@ void fill_info(const ufem::Plan& P, ufem_info* I) {
   I->n_active = (int64_t)P.active.size();
   I->n_inside = (int64_t)P.inside.size();
   I->n_cut = (int64_t)P.cut.size();
-  I->n_dofs = P.n_dofs();
+  I->n_dofs = P.n_space_dofs();
+  I->n_cell_dofs = P.n_dofs();
   I->n_faces = (int64_t)P.faces.size();
   I->n_faces_str = P.n_faces_str;
   I->n_faces_cut = P.n_faces_cut;
@@ -191,6 +192,12 @@ struct ufem_op {
           *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   int32_t* cut_rank = nullptr;      // active ranks of the cut cells
+  // continuous space: P (cell DoF -> node), P^T (node -> its cell DoFs) and
+  // three cell-layout vectors (float64 size, shared by both precisions)
+  int32_t* cell_node = nullptr;
+  int64_t* node_ptr = nullptr;
+  int32_t* node_src = nullptr;
+  void* cvec[3] = {nullptr, nullptr, nullptr};
   void* cmat[2] = {nullptr, nullptr};  // mixed evaluation: element matrices per precision
   bool mixed = false;
   // per-precision data
@@ -301,11 +308,38 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.hs = (T)std::pow(P.h, P.dim - 2);
   a.tau = (T)P.tau;
   a.gamma = (T)P.gamma;
-  a.terms = terms;
+  a.terms = P.cg ? (terms & ~UFEM_TERM_SIPG) : terms;  // no SIPG term in the continuous space
   a.parts = 15;
   a.max_blocks = max_blocks;
   a.gp_volume = P.gp_kind != UFEM_GP_FACE ? 1 : 0;
   return a;
+}
+
+// One apply v = A u of the space on `st` (stages `part` of the cell-DoF
+// operator; the continuous space takes the whole apply: P, the cell
+// operator, P^T).  adjoint: v = A^T w with w in `u`, u in `y`, and dkappa.
+template <typename T>
+static hipError_t run_apply(ufem_op* op, int prec, int part, const void* u, void* v, const void* y, void* dk,
+                            bool adjoint, hipStream_t st) {
+  auto a = op->args<T>(op->prec[prec]);
+  a.parts = part;
+  const ufem::Plan& P = op->P;
+  if (!P.cg)
+    return ufem::launch_operator<T>(a, P.dim, P.p, (const T*)(adjoint ? y : u), (T*)v, (const T*)(adjoint ? u : nullptr),
+                                    (T*)dk, adjoint, st);
+  const int64_t nc = P.n_dofs();
+  hipError_t e = ufem::launch_gather(prec, nc, op->cell_node, u, op->cvec[0], st);
+  if (e == hipSuccess && adjoint) e = ufem::launch_gather(prec, nc, op->cell_node, y, op->cvec[2], st);
+  if (e == hipSuccess)
+    e = ufem::launch_operator<T>(a, P.dim, P.p, (const T*)(adjoint ? op->cvec[2] : op->cvec[0]), (T*)op->cvec[1],
+                                 (const T*)(adjoint ? op->cvec[0] : nullptr), (T*)dk, adjoint, st);
+  if (e == hipSuccess) e = ufem::launch_scatter(prec, P.n_nodes, op->node_ptr, op->node_src, op->cvec[1], v, st);
+  return e;
+}
+
+static hipError_t run_apply_p(ufem_op* op, int prec, int part, const void* u, void* v, hipStream_t st) {
+  return prec == UFEM_F64 ? run_apply<double>(op, prec, part, u, v, nullptr, nullptr, false, st)
+                          : run_apply<float>(op, prec, part, u, v, nullptr, nullptr, false, st);
 }
 
 extern "C" {
@@ -668,6 +702,19 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       delete op;
       return rc;
     }
+    if (P.cg) {
+      std::vector<int32_t> src(P.node_src.begin(), P.node_src.end());
+      if ((rc = op->upload((void**)&op->cell_node, P.cell_node)) || (rc = op->upload((void**)&op->node_ptr, P.node_ptr)) ||
+          (rc = op->upload((void**)&op->node_src, src))) {
+        delete op;
+        return rc;
+      }
+      for (int i = 0; i < 3; ++i)
+        if ((rc = op->alloc(&op->cvec[i], (size_t)P.n_dofs() * sizeof(double)))) {
+          delete op;
+          return rc;
+        }
+    }
     std::vector<double> tab = make_tables(P);
     if ((rc = op->upload_prec<double>(op->prec[0], tab)) || (rc = op->upload_prec<float>(op->prec[1], tab))) {
       delete op;
@@ -805,21 +852,12 @@ int ufem_apply_part(ufem_op* op, int32_t precision, int32_t part, const void* u,
   if (!op || !u || !v) return fail(UFEM_EINVAL, "ufem_apply: null argument");
   if (part < 1 || part > UFEM_PART_ALL) return fail(UFEM_EINVAL, "ufem_apply_part: part must be a non-empty mask of UFEM_PART_* bits");
   if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_apply: bad precision");
-  const size_t bytes = (size_t)op->P.n_dofs() * (precision == UFEM_F64 ? 8 : 4);
+  if (op->P.cg && part != UFEM_PART_ALL)
+    return fail(UFEM_EUNSUPPORTED, "ufem_apply_part: the continuous space applies all stages at once");
+  const size_t bytes = (size_t)op->P.n_space_dofs() * (precision == UFEM_F64 ? 8 : 4);
   if (overlap(u, v, bytes)) return fail(UFEM_EINVAL, "ufem_apply: u and v overlap");
   DeviceGuard g(op->device);
-  hipError_t e;
-  if (precision == UFEM_F64) {
-    auto a = op->args<double>(op->prec[0]);
-    a.parts = part;
-    e = ufem::launch_operator<double>(a, op->P.dim, op->P.p, (const double*)u, (double*)v, nullptr, nullptr, false,
-                                      (hipStream_t)stream);
-  } else {
-    auto a = op->args<float>(op->prec[1]);
-    a.parts = part;
-    e = ufem::launch_operator<float>(a, op->P.dim, op->P.p, (const float*)u, (float*)v, nullptr, nullptr, false,
-                                     (hipStream_t)stream);
-  }
+  hipError_t e = run_apply_p(op, precision, part, u, v, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(e, "ufem_apply: launch");
   return UFEM_OK;
 }
@@ -829,7 +867,7 @@ int ufem_apply_adjoint(ufem_op* op, int32_t precision, const void* w, const void
   if (!op || !w || !u || !ATw) return fail(UFEM_EINVAL, "ufem_apply_adjoint: null argument");
   if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_apply_adjoint: bad precision");
   const size_t s = precision == UFEM_F64 ? 8 : 4;
-  const size_t bytes = (size_t)op->P.n_dofs() * s;
+  const size_t bytes = (size_t)op->P.n_space_dofs() * s;
   if (overlap(w, ATw, bytes) || overlap(u, ATw, bytes)) return fail(UFEM_EINVAL, "ufem_apply_adjoint: output overlaps input");
   if (dkappa) {
     const size_t kb = (size_t)op->P.seg[5] * s;
@@ -837,13 +875,9 @@ int ufem_apply_adjoint(ufem_op* op, int32_t precision, const void* w, const void
       return fail(UFEM_EINVAL, "ufem_apply_adjoint: dkappa overlaps a vector");
   }
   DeviceGuard g(op->device);
-  hipError_t e;
-  if (precision == UFEM_F64)
-    e = ufem::launch_operator<double>(op->args<double>(op->prec[0]), op->P.dim, op->P.p, (const double*)u,
-                                      (double*)ATw, (const double*)w, (double*)dkappa, true, (hipStream_t)stream);
-  else
-    e = ufem::launch_operator<float>(op->args<float>(op->prec[1]), op->P.dim, op->P.p, (const float*)u,
-                                     (float*)ATw, (const float*)w, (float*)dkappa, true, (hipStream_t)stream);
+  hipError_t e = precision == UFEM_F64
+                     ? run_apply<double>(op, precision, 15, w, ATw, u, dkappa, true, (hipStream_t)stream)
+                     : run_apply<float>(op, precision, 15, w, ATw, u, dkappa, true, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(e, "ufem_apply_adjoint: launch");
   return UFEM_OK;
 }
@@ -853,7 +887,7 @@ int ufem_cg_iterate(ufem_op* op, int32_t precision, int32_t n_iter, void* x, voi
   if (!op || !x || !r || !p || !ap || !scal) return fail(UFEM_EINVAL, "ufem_cg_iterate: null argument");
   if (n_iter < 0) return fail(UFEM_EINVAL, "ufem_cg_iterate: n_iter < 0");
   if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_cg_iterate: bad precision");
-  const size_t bytes = (size_t)op->P.n_dofs() * (precision == UFEM_F64 ? 8 : 4);
+  const size_t bytes = (size_t)op->P.n_space_dofs() * (precision == UFEM_F64 ? 8 : 4);
   const void* vec[4] = {x, r, p, ap};
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j)
@@ -861,18 +895,9 @@ int ufem_cg_iterate(ufem_op* op, int32_t precision, int32_t n_iter, void* x, voi
   for (int i = 0; i < 4; ++i)
     if (overlap2(scal, 4 * sizeof(double), vec[i], bytes)) return fail(UFEM_EINVAL, "ufem_cg_iterate: scal overlaps a vector");
   DeviceGuard g(op->device);
-  const int64_t n = op->P.n_dofs();
+  const int64_t n = op->P.n_space_dofs();
   for (int it = 0; it < n_iter; ++it) {
-    hipError_t e;
-    if (precision == UFEM_F64) {
-      auto a = op->args<double>(op->prec[0]);
-      e = ufem::launch_operator<double>(a, op->P.dim, op->P.p, (const double*)p, (double*)ap, nullptr, nullptr, false,
-                                        (hipStream_t)stream);
-    } else {
-      auto a = op->args<float>(op->prec[1]);
-      e = ufem::launch_operator<float>(a, op->P.dim, op->P.p, (const float*)p, (float*)ap, nullptr, nullptr, false,
-                                       (hipStream_t)stream);
-    }
+    hipError_t e = run_apply_p(op, precision, 15, p, ap, (hipStream_t)stream);
     if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate: apply");
     e = ufem::launch_cg_tail(precision, n, x, r, p, ap, scal, (hipStream_t)stream);
     if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate: vector update");
@@ -886,7 +911,7 @@ int ufem_cg_iterate_static(ufem_op* op, int32_t precision, int32_t n_iter, void*
   if (n_iter < 0) return fail(UFEM_EINVAL, "ufem_cg_iterate_static: n_iter < 0");
   if (precision != UFEM_F64 && precision != UFEM_F32) return fail(UFEM_EINVAL, "ufem_cg_iterate_static: bad precision");
   const size_t s = precision == UFEM_F64 ? 8 : 4;
-  const size_t bytes = (size_t)op->P.n_dofs() * s;
+  const size_t bytes = (size_t)op->P.n_space_dofs() * s;
   if (bytes > ufem::kStaticScratchBytes - ufem::kStaticCgScalarBytes)
     return fail(UFEM_EINVAL, "ufem_cg_iterate_static: n_dofs exceeds the static workspace (" +
                                  std::to_string((ufem::kStaticScratchBytes - ufem::kStaticCgScalarBytes) / s) +
@@ -903,17 +928,12 @@ int ufem_cg_iterate_static(ufem_op* op, int32_t precision, int32_t n_iter, void*
   double* scal = (double*)ws;
   void* ap = ws + ufem::kStaticCgScalarBytes;
   DeviceGuard g(op->device);
-  const int64_t n = op->P.n_dofs();
+  const int64_t n = op->P.n_space_dofs();
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = ufem::launch_cg_static_begin(precision, n, r, scal, st);
   if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate_static: r.r");
   for (int it = 0; it < n_iter; ++it) {
-    if (precision == UFEM_F64)
-      e = ufem::launch_operator<double>(op->args<double>(op->prec[0]), op->P.dim, op->P.p, (const double*)p,
-                                        (double*)ap, nullptr, nullptr, false, st);
-    else
-      e = ufem::launch_operator<float>(op->args<float>(op->prec[1]), op->P.dim, op->P.p, (const float*)p,
-                                       (float*)ap, nullptr, nullptr, false, st);
+    e = run_apply_p(op, precision, 15, p, ap, st);
     if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate_static: apply");
     e = ufem::launch_cg_tail(precision, n, x, r, p, ap, scal, st);
     if (e != hipSuccess) return hipfail(e, "ufem_cg_iterate_static: vector update");

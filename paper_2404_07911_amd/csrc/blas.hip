@@ -288,3 +288,55 @@ hipError_t launch_matrix_cast(int64_t n, const double* in, float* out, hipStream
 }
 
 }  // namespace ufem
+
+// ------------------------------------------- continuous space: P and P^T
+namespace ufem {
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(256) gather_kernel(int64_t n_cell, const int32_t* __restrict__ cell_node,
+                                                     const T* __restrict__ u, T* __restrict__ ucell) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_cell; i += (int64_t)gridDim.x * blockDim.x)
+    ucell[i] = u[cell_node[i]];
+}
+
+// every node sums its cells' contributions in the fixed order of node_src
+// (no atomics: repeated applies are bit-identical)
+template <typename T>
+__global__ void __launch_bounds__(256) scatter_kernel(int64_t n_nodes, const int64_t* __restrict__ node_ptr,
+                                                      const int32_t* __restrict__ node_src,
+                                                      const T* __restrict__ vcell, T* __restrict__ v) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_nodes; j += (int64_t)gridDim.x * blockDim.x) {
+    T s = 0;
+    for (int64_t k = node_ptr[j]; k < node_ptr[j + 1]; ++k) s += vcell[node_src[k]];
+    v[j] = s;
+  }
+}
+
+int grid_for3(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
+
+}  // namespace
+
+hipError_t launch_gather(int prec, int64_t n_cell, const int32_t* cell_node, const void* u, void* ucell,
+                         hipStream_t s) {
+  if (n_cell <= 0) return hipSuccess;
+  if (prec == 0)
+    gather_kernel<double><<<grid_for3(n_cell), 256, 0, s>>>(n_cell, cell_node, (const double*)u, (double*)ucell);
+  else
+    gather_kernel<float><<<grid_for3(n_cell), 256, 0, s>>>(n_cell, cell_node, (const float*)u, (float*)ucell);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int prec, int64_t n_nodes, const int64_t* node_ptr, const int32_t* node_src,
+                          const void* vcell, void* v, hipStream_t s) {
+  if (n_nodes <= 0) return hipSuccess;
+  if (prec == 0)
+    scatter_kernel<double><<<grid_for3(n_nodes), 256, 0, s>>>(n_nodes, node_ptr, node_src, (const double*)vcell,
+                                                               (double*)v);
+  else
+    scatter_kernel<float><<<grid_for3(n_nodes), 256, 0, s>>>(n_nodes, node_ptr, node_src, (const float*)vcell,
+                                                              (float*)v);
+  return hipGetLastError();
+}
+
+}  // namespace ufem

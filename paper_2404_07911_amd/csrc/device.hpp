@@ -151,6 +151,13 @@ hipError_t launch_unit_rows(int prec, int64_t n_dofs, int nd, int n_cut, const i
 hipError_t launch_matrix_column(int prec, int nd, int n_cut, const int32_t* cut_rank, int j, const void* v, void* mat,
                                 hipStream_t s);
 hipError_t launch_matrix_cast(int64_t n, const double* in, float* out, hipStream_t s);
+
+// Continuous space (blas.hip): ucell = P u (the node values copied into the
+// cell DoFs), v = P^T vcell (each node sums its cell DoFs in a fixed order).
+hipError_t launch_gather(int prec, int64_t n_cell, const int32_t* cell_node, const void* u, void* ucell,
+                         hipStream_t s);
+hipError_t launch_scatter(int prec, int64_t n_nodes, const int64_t* node_ptr, const int32_t* node_src,
+                          const void* vcell, void* v, hipStream_t s);
 // Static workspace of ufem_cg_iterate_static (blas.hip): 64 MiB for A p after
 // 256 bytes of CG scalars.  static_scratch_address gives the calling
 // thread's current device's copy.

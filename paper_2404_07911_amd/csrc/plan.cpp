@@ -732,6 +732,7 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
   if (pr.gp_jmin < 0 || pr.gp_jmin > pr.degree + 1) return "gp_jmin out of range";
   if (pr.gp_kind != UFEM_GP_FACE && pr.gp_kind != UFEM_GP_VOLUME && pr.gp_kind != UFEM_GP_VOLUME_ALL)
     return "unknown ghost-penalty kind";
+  if (pr.space != UFEM_SPACE_DG && pr.space != UFEM_SPACE_CG) return "unknown space";
   double cells = std::pow((double)pr.n, pr.dim);
   if (cells > 2.2e9) return "background mesh too large";
   P.prob = pr;
@@ -796,6 +797,52 @@ std::string build_plan(const ufem_problem& pr, Plan& P, int* code) {
   P.inside.clear();
   P.cut.clear();
   for (size_t r = 0; r < P.active.size(); ++r) (P.cls[P.active[r]] == kInside ? P.inside : P.cut).push_back((int32_t)r);
+
+  // -- continuous space: the node lattice of (n p + 1)^dim Gauss-Lobatto
+  // nodes, the nodes of active cells numbered in lattice order
+  P.cg = pr.space == UFEM_SPACE_CG;
+  P.n_nodes = 0;
+  P.cell_node.clear();
+  P.node_ptr.clear();
+  P.node_src.clear();
+  if (P.cg) {
+    const int64_t L1 = (int64_t)n * P.p + 1;
+    int64_t lat = 1;
+    for (int a = 0; a < dim; ++a) lat *= L1;
+    if (lat > (int64_t)2000000000) { *code = UFEM_EUNSUPPORTED; return "node lattice too large"; }
+    std::vector<int32_t> lat2node((size_t)lat, -1);
+    const int nd = P.nd(), K = P.k;
+    auto lattice = [&](int32_t b, int l) {
+      int64_t g = 0, stride = 1;
+      int32_t rem = b;
+      int rl = l;
+      for (int a = 0; a < dim; ++a) {
+        const int64_t I = (int64_t)(rem % n) * P.p + (rl % K);
+        rem /= n;
+        rl /= K;
+        g += I * stride;
+        stride *= L1;
+      }
+      return g;
+    };
+    for (int32_t b : P.active)
+      for (int l = 0; l < nd; ++l) lat2node[(size_t)lattice(b, l)] = 0;
+    for (int64_t g = 0; g < lat; ++g)
+      if (lat2node[(size_t)g] == 0) lat2node[(size_t)g] = (int32_t)(P.n_nodes++) + 1;
+    P.cell_node.resize((size_t)P.n_dofs());
+    std::vector<int64_t> cnt((size_t)P.n_nodes + 1, 0);
+    for (size_t r = 0; r < P.active.size(); ++r)
+      for (int l = 0; l < nd; ++l) {
+        const int32_t node = lat2node[(size_t)lattice(P.active[r], l)] - 1;
+        P.cell_node[r * nd + l] = node;
+        ++cnt[(size_t)node + 1];
+      }
+    P.node_ptr.assign((size_t)P.n_nodes + 1, 0);
+    for (int64_t i = 0; i < P.n_nodes; ++i) P.node_ptr[i + 1] = P.node_ptr[i] + cnt[(size_t)i + 1];
+    P.node_src.assign((size_t)P.n_dofs(), 0);
+    std::vector<int64_t> fill(P.node_ptr.begin(), P.node_ptr.end() - 1);
+    for (int64_t i = 0; i < P.n_dofs(); ++i) P.node_src[(size_t)fill[(size_t)P.cell_node[i]]++] = i;
+  }
 
   // -- faces
   int64_t stride[3] = {1, n, (int64_t)n * n};

@@ -68,7 +68,19 @@ struct Plan {
   int64_t n_fallback = 0;
   int64_t max_qp_cut_cell = 0;
 
+  // cell DoFs: the discontinuous layout every kernel works on
   int64_t n_dofs() const { return (int64_t)active.size() * nd(); }
+  // continuous space (FE_Q): the Gauss-Lobatto nodes of the active cells on
+  // the global node lattice, numbered in lattice order; cell_node maps cell
+  // DoF r * nd + l to its node, node_ptr / node_src list every node's cell
+  // DoFs in increasing order
+  bool cg = false;
+  int64_t n_nodes = 0;
+  std::vector<int32_t> cell_node;
+  std::vector<int64_t> node_ptr;
+  std::vector<int64_t> node_src;
+  // DoFs of the space: nodes (continuous) or cell DoFs (discontinuous)
+  int64_t n_space_dofs() const { return cg ? n_nodes : n_dofs(); }
   int nd() const { int r = 1; for (int a = 0; a < dim; ++a) r *= k; return r; }
   int nf() const { int r = 1; for (int a = 0; a < dim - 1; ++a) r *= k; return r; }
   void cell_lo(int32_t b, double* x) const;

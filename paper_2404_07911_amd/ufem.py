@@ -35,6 +35,7 @@ class Problem:
     gp_flat: bool = False
     plane: tuple | None = None
     gp_kind: str = "face"  # "face", "volume" (stable neighbours) or "volume_all"
+    space: str = "dg"  # "dg" (SIPG) or "cg" (continuous FE_Q)
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -64,6 +65,9 @@ class Problem:
         if self.gp_kind not in kinds:
             raise ValueError(f"gp_kind must be one of {sorted(kinds)}")
         s.gp_kind = kinds[self.gp_kind]
+        if self.space not in ("dg", "cg"):
+            raise ValueError("space must be 'dg' or 'cg'")
+        s.space = L.SPACE_CG if self.space == "cg" else L.SPACE_DG
         if self.plane is not None:
             nrm = np.asarray(self.plane[0], dtype=np.float64).reshape(-1)
             s.levelset = L.LEVELSET_PLANE

@@ -205,3 +205,21 @@ def test_import_quadrature_rejects_bad_rules():
     inf = L.ufem_info()
     L.check(L.lib().ufem_plan_info(pl.handle, C.byref(inf)))
     assert inf.as_dict() == before
+
+
+@pytest.mark.parametrize("name", ["disk2d_p2", "ball3d_p2", "balls3d_p2", "plane3d_p2", "ball3d_p2_vgp"])
+def test_continuous_space_node_count(name):
+    """The continuous space's DoFs: the Gauss-Lobatto nodes of the active
+    cells on the node lattice (the oracle's count); the cell-DoF layout and
+    the quadrature stay those of the discontinuous plan."""
+    from oracle.operator import UnfittedCG
+    from paper_2404_07911_amd import Plan, Problem
+
+    wl, _ = make_case(name)
+    opts = case_options(name)
+    pl = Plan(Problem.from_workload(wl, space="cg", **opts))
+    dg = Plan(Problem.from_workload(wl, **opts))
+    o = UnfittedCG(wl.dim, wl.n, wl.degree, wl.centers, wl.radii, wl.lo, wl.hi, plane=wl.plane, **opts)
+    assert pl.info["n_dofs"] == o.n_dofs
+    assert pl.info["n_cell_dofs"] == dg.info["n_dofs"] == o.dg.n_dofs
+    assert pl.info["seg"] == dg.info["seg"]
