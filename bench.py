@@ -324,10 +324,19 @@ def run_solve(op, plan, rng, tol, inner_rtol):
     ustar = torch.from_numpy(ui.uniform_vector(rng, n)).cuda()
     b = op.apply(ustar)
     x = torch.zeros_like(b)
-    (x, i64), t64 = timed(lambda: device_cg(op, b, x, rtol=tol, maxiter=400000), ops)
+    last = [time.perf_counter()]
+
+    def tick(it, res):
+        # a progress line at most every 20 s (long solves stay visibly alive)
+        if time.perf_counter() - last[0] > 20.0:
+            last[0] = time.perf_counter()
+            progress(f"solve: {it} iterations, relative residual {res:.2e}")
+
+    (x, i64), t64 = timed(lambda: device_cg(op, b, x, rtol=tol, maxiter=400000, progress=tick), ops)
     r = op.apply(x)
     res64 = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
-    (u, idc), tdc = timed(lambda: device_defect_correction(op, b, tol=tol, inner_rtol=inner_rtol), ops)
+    progress(f"solve: FP64 CG done ({i64['iterations']} iterations, {t64:.1f} s); defect correction")
+    (u, idc), tdc = timed(lambda: device_defect_correction(op, b, tol=tol, inner_rtol=inner_rtol, progress=tick), ops)
     r = op.apply(u)
     resdc = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
     err = float(torch.linalg.norm(u - ustar) / torch.linalg.norm(ustar))
@@ -347,13 +356,16 @@ def run_solve(op, plan, rng, tol, inner_rtol):
     }
 
 
-def workload_text(wl):
+def workload_text(wl, space="dg", gp="face"):
     if wl.plane is not None:
         geo = f"plane n={list(np.round(wl.plane[0], 6))} offset {wl.plane[1]:.6f}"
     else:
         geo = f"{len(wl.radii)} ball(s)"
-    return (f"{wl.name}: {wl.dim}D SIPG DG p={wl.degree}, {wl.n}^{wl.dim} background cells on [-1,1]^{wl.dim}, "
-            f"{geo}, Nitsche + face ghost penalty" + (", kappa field" if wl.name == "kappa3d" else ""))
+    disc = "SIPG DG" if space == "dg" else "continuous FE_Q"
+    gpt = {"face": "face ghost penalty", "volume": "volume ghost penalty (stable neighbours)",
+           "volume_all": "volume ghost penalty (all neighbours)"}[gp]
+    return (f"{wl.name}: {wl.dim}D {disc} p={wl.degree}, {wl.n}^{wl.dim} background cells on [-1,1]^{wl.dim}, "
+            f"{geo}, Nitsche + {gpt}" + (", kappa field" if wl.name == "kappa3d" else ""))
 
 
 def solve_mode(args, wl, rng, plan, op, t_setup):
@@ -460,6 +472,10 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-one-core", action="store_true", help="oracle baseline on one core only")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve comparison of the default line")
+    ap.add_argument("--space", default="dg", choices=["dg", "cg"],
+                    help="dg: SIPG discontinuous space (default); cg: continuous FE_Q space")
+    ap.add_argument("--gp", default="face", choices=["face", "volume", "volume_all"],
+                    help="ghost penalty: face (default), volume (stable neighbours), volume_all")
     ap.add_argument("--mixed", action="store_true",
                     help="mixed evaluation: the cut cells' volume and interface terms as precomputed element matrices")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
@@ -490,9 +506,9 @@ def main(argv=None):
 
     wl, rng = make_workload(args.workload, args.seed, args.n, args.degree, args.layer)
 
-    progress(f"plan and setup of {wl.name} p={wl.degree} n={wl.n}")
+    progress(f"plan and setup of {wl.name} p={wl.degree} n={wl.n} ({args.space}, {args.gp} ghost penalty)")
     t0 = time.perf_counter()
-    plan = Plan(Problem.from_workload(wl))
+    plan = Plan(Problem.from_workload(wl, space=args.space, gp_kind=args.gp))
     op = Operator(plan, device=0)
     t_setup = time.perf_counter() - t0
     info = plan.info
@@ -537,7 +553,13 @@ def main(argv=None):
                 if ev is not None:
                     ev[k].record(stream)
                 k += 1
-                op.apply_part(part, U, V)
+                if args.space == "cg":
+                    # the continuous space applies every stage at once (node
+                    # gather and sums around the cell kernels): timed whole
+                    if part == 3:
+                        op.apply(U, V)
+                else:
+                    op.apply_part(part, U, V)
         if ev is not None:
             ev[2 * NS].record(stream)
         op.apply_adjoint(W64, U64[j], ATW, DK)
@@ -584,11 +606,17 @@ def main(argv=None):
     dom = max(ms64, key=ms64.get)
     dom_ms = ms64[dom]
     achieved = bytes64[dom] / (dom_ms * 1e-3) / 1e9
+    if args.space == "cg":
+        # one timed launch sequence per apply: the whole apply is the unit
+        dom, dom_ms = "total", t64 * 1e3
+        achieved = bytes64["total"] / t64 / 1e9
     ctr = load_counters(f"{args.workload}_p{wl.degree}_n{wl.n}_{dom}_f64")
     traffic = ctr["hbm_bytes_per_launch"] if ctr else None
     roofline = {
         "bound": "hbm",
-        "kernel": f"{(STAGE_KERNELS_MIXED if args.mixed else STAGE_KERNELS)[dom]}, K={wl.degree + 1}, D={wl.dim}, double",
+        "kernel": ("whole apply of the continuous space (node gather, cell kernels, node sums)" if dom == "total"
+                   else f"{(STAGE_KERNELS_MIXED if args.mixed else STAGE_KERNELS)[dom]}")
+        + f", K={wl.degree + 1}, D={wl.dim}, double",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -612,7 +640,7 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": workload_text(wl),
+            "workload": workload_text(wl, args.space, args.gp),
             "degree": wl.degree,
             "background_cells": wl.n,
             "active_dofs": n,
@@ -623,6 +651,9 @@ def main(argv=None):
             "cut_cell_ratio": info["n_cut"] / max(1, info["n_active"]),
             "evaluation": "mixed (cut-cell volume and interface terms as element matrices)" if args.mixed
             else "matrix-free",
+            "space": "continuous Q_p (FE_Q), Poisson + Nitsche" if args.space == "cg" else "discontinuous Q_p, SIPG",
+            "ghost_penalty": args.gp,
+            "cell_dofs": info["n_cell_dofs"],
             "quadrature_points": info["n_qp"],
             "parallelism": "single GPU",
         },
@@ -634,7 +665,8 @@ def main(argv=None):
         "adjoint_ms": tadj * 1e3,
         "kernels_ms": {**{f"{nm}_f64": ms64[nm] for nm in names}, **{f"{nm}_f32": ms32[nm] for nm in names},
                        "adjoint_f64": adj},
-        "kernels_hbm_frac_f64": {nm: bytes64[nm] / (ms64[nm] * 1e-3) / 1e9 / HBM_PEAK_GBS for nm in names},
+        "kernels_hbm_frac_f64": ({nm: bytes64[nm] / (ms64[nm] * 1e-3) / 1e9 / HBM_PEAK_GBS for nm in names}
+                                 if args.space == "dg" else None),
         "apply_hbm_frac_f64": apply_gbs / HBM_PEAK_GBS,
         "apply_hbm_frac_f32": bytes32["total"] / t32 / 1e9 / HBM_PEAK_GBS,
         "model_gflop_per_apply": flops / 1e9 if flops else None,
@@ -658,12 +690,14 @@ def main(argv=None):
         out["copy_probe"] = {"bytes_read": a.numel() * 8, "ms": e0.elapsed_time(e1),
                              "gbs": 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9}
     rows1 = None
+    if args.space == "cg" or args.gp != "face":
+        args.no_cpu_baseline = True  # the baseline and the stored rows are the default discretisation's
     if not args.no_cpu_baseline:
         progress("oracle baseline on the host cores")
         out["cpu_baseline"], rows1 = cpu_baseline(args, wl, u_host, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
-    out["error_vs_oracle"] = oracle_errors(wl, info, plan.cells(), v64_h, v32_h, atw_h,
-                                           dk_h, rows1)
+    out["error_vs_oracle"] = (oracle_errors(wl, info, plan.cells(), v64_h, v32_h, atw_h, dk_h, rows1)
+                              if args.space == "dg" and args.gp == "face" else None)
     if sol is not None:
         out["solve"] = sol
     print(json.dumps(out), flush=True)

@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KronOcc
       glb_line_load<K, D, 0>(x + (int64_t)r * ND, bx, ux);
 #pragma unroll
       for (int s = 0; s < 2 * D; ++s) {
-        if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+        if (!((((fl >> (kFlagStr + s)) & (a.terms >> 1)) | ((fl >> (kFlagGP + s)) & (a.terms >> 3))) & 1)) continue;
         const T* un = x + (int64_t)nbr[s] * ND;
         const int ax = s >> 1;
         if (ax == 0) glb_line_load<K, D, 0>(un, bx, nb[s]);
@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 
 #pragma unroll
         for (int s = 0; s < 2 * D; ++s) {
           fkall[s] = kface[(int64_t)ci * 2 * D + s];
-          if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+          if (!((((fl >> (kFlagStr + s)) & (a.terms >> 1)) | ((fl >> (kFlagGP + s)) & (a.terms >> 3))) & 1)) continue;
           const T* un = x + (int64_t)nbr[s] * ND;
           const int ax = s >> 1;
           if (ax == 0) glb_line_load<K, D, 0>(un, bx, nball[s]);
@@ -657,7 +657,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 
         for (int q = 0; q < K; ++q) nbl[side][q] = 0;
         if (!valid) continue;
         fko[side] = kface[(int64_t)ci * 2 * D + s];
-        if (!(((fl >> (kFlagStr + s)) | (fl >> (kFlagGP + s))) & 1)) continue;
+        if (!((((fl >> (kFlagStr + s)) & (a.terms >> 1)) | ((fl >> (kFlagGP + s)) & (a.terms >> 3))) & 1)) continue;
         const int ns = s == 0 ? nbr[0] : s == 1 ? nbr[1] : s == 2 ? nbr[2] : s == 3 ? nbr[3] : s == 4 ? nbr[4] : nbr[5];
         const T* un = x + (int64_t)ns * ND + gbase;
 #pragma unroll

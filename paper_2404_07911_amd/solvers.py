@@ -206,12 +206,13 @@ def defect_correction(apply64, apply32, b, ops, tol=1e-10, inner_rtol=1e-4, max_
     return u, info
 
 
-def device_cg(op, b, x, rtol=1e-10, maxiter=100000, chunk=32, rnorm0=None):
+def device_cg(op, b, x, rtol=1e-10, maxiter=100000, chunk=32, rnorm0=None, progress=None):
     """CG for op's matrix with every iteration on the device
     (`ufem_cg_iterate`): the host reads the residual norm once per `chunk`
     iterations, so up to chunk - 1 iterations beyond the target may run.
-    b, x: device tensors of one precision (x updated in place).  Returns
-    (x, info) like `cg`."""
+    b, x: device tensors of one precision (x updated in place).  progress,
+    if given, is called with (iterations, relative residual) after every
+    chunk.  Returns (x, info) like `cg`."""
     import torch
 
     ops = DeviceOps(b.device.index or 0)
@@ -240,6 +241,8 @@ def device_cg(op, b, x, rtol=1e-10, maxiter=100000, chunk=32, rnorm0=None):
         it += n
         sc = scal.cpu()
         rr = float(sc[0])
+        if progress is not None:
+            progress(it, math.sqrt(max(rr, 0.0)) / bnorm)
         if sc[3] != 0.0:
             info["breakdown"] = True
             break
@@ -250,7 +253,7 @@ def device_cg(op, b, x, rtol=1e-10, maxiter=100000, chunk=32, rnorm0=None):
 
 
 def device_defect_correction(op, b, tol=1e-10, inner_rtol=1e-4, max_outer=60, max_inner=100000, chunk=32,
-                             stagnation_factor=0.5, stagnation_window=3):
+                             stagnation_factor=0.5, stagnation_window=3, progress=None):
     """`defect_correction` with the FP32 inner solves done by `device_cg`
     (b: float64 device tensor); an inner solve stops at inner_rtol or, when
     less is needed to reach tol, at 0.3 tol ||b|| / ||r|| (at most 1e-2).
@@ -286,7 +289,7 @@ def device_defect_correction(op, b, tol=1e-10, inner_rtol=1e-4, max_outer=60, ma
         d32 = torch.zeros_like(r32)
         # the last correction only has to close the remaining gap to tol
         rtol_k = min(1e-2, max(inner_rtol, 0.3 * tol * bnorm / rnorm))
-        _, ii = device_cg(op, r32, d32, rtol=rtol_k, maxiter=max_inner, chunk=chunk, rnorm0=1.0)
+        _, ii = device_cg(op, r32, d32, rtol=rtol_k, maxiter=max_inner, chunk=chunk, rnorm0=1.0, progress=progress)
         inner_total += ii["iterations"]
         info["inner_breakdown"] |= ii["breakdown"]
         ops.copy(d64, d32)
