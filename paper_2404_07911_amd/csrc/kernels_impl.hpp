@@ -198,20 +198,23 @@ __device__ __forceinline__ void line_faces(const T* __restrict__ tab, const DevA
     const T* un = side ? nhi : nlo;
     const T sigma = side ? T(1) : T(-1);
     if (fs) {
-      T ov = 0, od = 0, nv = 0, nd = 0;
+      // the basis is nodal on Gauss-Lobatto points, so a line's value at a
+      // face is its end-point DoF (own: node io, neighbour: node in) and
+      // the value test functions of the face are the unit vector at io
+      const int io = side ? K - 1 : 0, in = side ? 0 : K - 1;
+      T od = 0, nd = 0;
 #pragma unroll
       for (int l = 0; l < K; ++l) {
-        ov += Eo[l] * uo[l];
         od += Eo[K + l] * uo[l];
-        nv += En[l] * un[l];
         nd += En[K + l] * un[l];
       }
-      const T J = sigma * (ov - nv);
+      const T J = sigma * (uo[io] - un[in]);
       const T Av = T(0.5) * (od + nd);
       const T cv = sigma * (a.gamma * J - Av);
       const T cd = T(-0.5) * J;
 #pragma unroll
-      for (int l = 0; l < K; ++l) R[l] += Eo[l] * cv + Eo[K + l] * cd;
+      for (int l = 0; l < K; ++l) R[l] += Eo[K + l] * cd;
+      R[io] += cv;
     }
     if (fg) {
       // face ghost penalty: sum_j gamma_j E^j_l (d^j u_own - d^j u_nb),
@@ -842,23 +845,32 @@ __device__ __forceinline__ void line_columns(const T* u, const T* V1, const T* d
   }
 }
 
-// store a line record (layout of LineShape) as record r of REC
+// the two parts of a line record (layout of LineShape), record r of REC:
+// the basis values of the fixed coordinates, and the point sums
 template <int K, int D, typename T>
-__device__ __forceinline__ void line_record(const T* V1, const T* dV1, const T* V2, const T* dV2, const T* D0,
-                                            const T* D1, const T* D2, T* REC, int r) {
+__device__ __forceinline__ void line_record_basis(const T* V1, const T* dV1, const T* V2, const T* dV2, T* REC, int r) {
   using LS = LineShape<K, D>;
   T* R = REC + r * LS::RSP;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     R[LS::V1 + i] = V1[i];
     R[LS::DV1 + i] = dV1[i];
-    R[LS::D0 + i] = D0[i];
-    R[LS::D1 + i] = D1[i];
     if constexpr (D == 3) {
       R[LS::V2 + i] = V2[i];
       R[LS::DV2 + i] = dV2[i];
-      R[LS::D2 + i] = D2[i];
     }
+  }
+}
+
+template <int K, int D, typename T>
+__device__ __forceinline__ void line_record_sums(const T* D0, const T* D1, const T* D2, T* REC, int r) {
+  using LS = LineShape<K, D>;
+  T* R = REC + r * LS::RSP;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    R[LS::D0 + i] = D0[i];
+    R[LS::D1 + i] = D1[i];
+    if constexpr (D == 3) R[LS::D2 + i] = D2[i];
   }
 }
 
@@ -926,6 +938,9 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
   }
   T c0[K], c1[K], c2[K];
   line_columns<K, D, KA>(Uo, V1, dV1, V2, dV2, c0, c1, c2);
+  // the basis parts of the record go out now, which frees their registers
+  // for the point loop
+  line_record_basis<K, D>(V1, dV1, V2, dV2, REC, r);
   T D0[K], D1[K], D2[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) { D0[i] = 0; D1[i] = 0; D2[i] = 0; }
@@ -967,7 +982,7 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
       }
     }
   }
-  line_record<K, D>(V1, dV1, V2, dV2, D0, D1, D2, REC, r);
+  line_record_sums<K, D>(D0, D1, D2, REC, r);
 }
 
 // Batched line kernels: one wave per batch of cut cells whose lines fit in
