@@ -189,7 +189,7 @@ struct ufem_op {
   int32_t* inside = nullptr;
   int64_t *kface_inside = nullptr, *kface_cut = nullptr;
   int32_t *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr, *fdesc = nullptr, *kinfo_inside = nullptr,
-          *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_bm = nullptr, *sf_bp = nullptr, *sf_ax = nullptr;
+          *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_first = nullptr;
   int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   int32_t* cut_rank = nullptr;      // active ranks of the cut cells
   // continuous space: P (cell DoF -> node), P^T (node -> its cell DoFs) and
@@ -286,9 +286,7 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.n_cu = n_cu;
   a.n_vbatch = n_vbatch;
   a.n_fbatch = n_fbatch;
-  a.sf_bm = sf_bm;
-  a.sf_bp = sf_bp;
-  a.sf_ax = sf_ax;
+  a.sf_first = sf_first;
   a.n_sfaces = n_sfaces;
   a.vol_x = (const T*)d.vol_x;
   a.vol_w = (const T*)d.vol_w;
@@ -634,16 +632,20 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
       desc = std::move(slots);
       desc.insert(desc.end(), ovf.begin(), ovf.end());
     };
-    // structured faces in kappa order (by lower cell, then axis: the faces
-    // of a wave share cells)
-    std::vector<int32_t> sbm, sbp, sax;
-    for (const ufem::Face& f : P.faces)
-      if (f.kind == ufem::kFaceStructured) {
-        sbm.push_back(P.rank[f.bm]);
-        sbp.push_back(P.rank[f.bp]);
-        sax.push_back(f.axis);
+    // structured faces in kappa order (by lower cell, then axis): the index
+    // of each active cell's first one
+    std::vector<int32_t> sff(na, 0);
+    int32_t n_sf = 0;
+    {
+      std::vector<int32_t> cnt(na, 0);
+      for (const ufem::Face& f : P.faces)
+        if (f.kind == ufem::kFaceStructured) ++cnt[P.rank[f.bm]];
+      for (size_t r = 0; r < na; ++r) {
+        sff[r] = n_sf;
+        n_sf += cnt[r];
       }
-    op->n_sfaces = (int32_t)sbm.size();
+    }
+    op->n_sfaces = n_sf;
     // per-position cell info of the Kronecker kernel's lists
     auto make_kinfo = [&](const std::vector<int32_t>& list) {
       std::vector<int32_t> ki(list.size() * 8, -1);
@@ -697,8 +699,7 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->kface_cut, kfcu)) ||
         (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
         (rc = op->upload((void**)&op->fbrec, fb)) || (rc = op->upload((void**)&op->fdesc, fl)) ||
-        (rc = op->upload((void**)&op->sf_bm, sbm)) || (rc = op->upload((void**)&op->sf_bp, sbp)) ||
-        (rc = op->upload((void**)&op->sf_ax, sax))) {
+        (rc = op->upload((void**)&op->sf_first, sff))) {
       delete op;
       return rc;
     }

@@ -98,10 +98,9 @@ struct DevArgs {
   const int32_t* fdesc;
   int32_t n_vbatch, n_fbatch;
   int32_t n_cu;  // compute units of the device (persistent grids)
-  // structured SIPG faces (kappa order): ranks of the lower / upper cell, axis
-  const int32_t* sf_bm;
-  const int32_t* sf_bp;
-  const int32_t* sf_ax;
+  // structured SIPG faces (kappa order: by lower cell, then axis): index of
+  // the first one whose lower cell is active cell r, per r
+  const int32_t* sf_first;
   int32_t n_sfaces;
   const T* vol_x;            // SoA: vol_x[a * n_vol + q]
   const T* vol_w;

@@ -1729,6 +1729,18 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
 
 // structured SIPG faces: traces of w and u at the Gauss-Lobatto face nodes
 // from both cells, interpolated to the face Gauss points
+// Structured SIPG faces of dL/dkappa, by groups of C consecutive active
+// cells (rank order): each cell takes its structured upper faces (slots
+// 2 ax + 1).  The group's DoFs of w and u are staged in LDS once and serve
+// the faces along every axis and, where a face's upper cell is in the group
+// (mostly the x neighbour), its other side too; other neighbours' lines
+// normal to the face come from memory.  Lane (c, f): cell c, face node f.
+// Per face: value jumps and normal-derivative averages of w and u on the
+// Gauss-Lobatto face nodes (the value trace is the end-point DoF of the
+// nodal basis), interpolated to the face Gauss points, and
+//   dk_q = w_q h^(d-2) (-{d_n w}[u] - [w]{d_n u} + gamma [w][u]).
+// The faces of a cell are consecutive in kappa order, by axis, from
+// sf_first[cell].
 template <int K, int D>
 struct FaceDkShape {
   static constexpr int NF = ipow(K, D - 1);
@@ -1739,6 +1751,7 @@ template <int K, int D, typename T>
 __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __restrict__ w, const T* __restrict__ u,
                                                      T* __restrict__ dk) {
   constexpr int ND = ipow(K, D), NF = FaceDkShape<K, D>::NF, C = FaceDkShape<K, D>::C;
+  __shared__ T X[C][2][ND];
   __shared__ T F[C][4][NF];
   const T* __restrict__ tab = a.tab;
   const T* S = tab + TabOff::S(K);
@@ -1749,55 +1762,84 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
   const int c = lane / NF, f = lane % NF;
   const bool active = c < C;
   const int cc = active ? c : 0;
-  for (int f0 = xcd_block() * C; f0 < a.n_sfaces; f0 += gridDim.x * C) {
-    const int fi = f0 + c;
-    const bool valid = active && fi < a.n_sfaces;
+  const bool sipg = (a.terms & 2) != 0;
+  for (int g0 = xcd_block() * C; g0 < a.n_active; g0 += gridDim.x * C) {
+    const int ci = g0 + c;
+    const bool valid = active && ci < a.n_active;
+    int4 k0 = make_int4(0, 0, 0, 0), k1 = make_int4(-1, -1, -1, -1);
+    int first = 0;
     if (valid) {
-      const int ax = a.sf_ax[fi];
-      const int64_t rm = a.sf_bm[fi], rp = a.sf_bp[fi];
+      k0 = reinterpret_cast<const int4*>(a.kinfo_all)[2 * ci];
+      k1 = reinterpret_cast<const int4*>(a.kinfo_all)[2 * ci + 1];
+      first = a.sf_first[ci];
+      // the cell's DoFs of w and u: lane f loads DoFs [f K, f K + K)
 #pragma unroll
-      for (int fld = 0; fld < 2; ++fld) {
-        const T* src = fld ? u : w;
-        T vm = 0, dm = 0, vp = 0, dp = 0;
-#pragma unroll
-        for (int l = 0; l < K; ++l) {
-          const int ci2 = D == 3 ? cell_index<K, D>(ax, f, l) : cell_index<K, D>(ax, f, l);
-          const T xm = src[rm * ND + ci2], xp = src[rp * ND + ci2];
-          vm += E1[l] * xm;
-          dm += E1[K + l] * xm;
-          vp += E0[l] * xp;
-          dp += E0[K + l] * xp;
-        }
-        F[cc][2 * fld][f] = vm - vp;
-        F[cc][2 * fld + 1][f] = T(0.5) * (dm + dp);
+      for (int q = 0; q < K; ++q) {
+        X[cc][0][f * K + q] = w[(int64_t)ci * ND + f * K + q];
+        X[cc][1][f * K + q] = u[(int64_t)ci * ND + f * K + q];
       }
     }
+    const int fl = k0.y;
+    const int up[3] = {k0.w, k1.y, k1.w};  // upper neighbours (slots 1, 3, 5)
     sync();
-    if (valid) {
-      T g[4];
-      const int q0 = f % K, q1 = f / K;
+    int nf_before = 0;
 #pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) {
-        T s2 = 0;
-        if constexpr (D == 3) {
+    for (int ax = 0; ax < D; ++ax) {
+      const bool has = valid && ((fl >> (kFlagStr + 2 * ax + 1)) & 1);
+      if (has) {
+        const int nr = up[ax];
+        const bool in_group = nr >= g0 && nr < g0 + C;
 #pragma unroll
-          for (int b = 0; b < K; ++b) {
-            T s1 = 0;
+        for (int fld = 0; fld < 2; ++fld) {
+          T xm[K], xp[K];
 #pragma unroll
-            for (int a2 = 0; a2 < K; ++a2) s1 += S[q0 * K + a2] * F[cc][k2][a2 + K * b];
-            s2 += S[q1 * K + b] * s1;
+          for (int l = 0; l < K; ++l) xm[l] = X[cc][fld][cell_index<K, D>(ax, f, l)];
+          if (in_group) {
+#pragma unroll
+            for (int l = 0; l < K; ++l) xp[l] = X[nr - g0][fld][cell_index<K, D>(ax, f, l)];
+          } else {
+            const T* src = fld ? u : w;
+#pragma unroll
+            for (int l = 0; l < K; ++l) xp[l] = src[(int64_t)nr * ND + cell_index<K, D>(ax, f, l)];
           }
-        } else {
+          T dm = 0, dp = 0;
 #pragma unroll
-          for (int a2 = 0; a2 < K; ++a2) s2 += S[q0 * K + a2] * F[cc][k2][a2];
+          for (int l = 0; l < K; ++l) {
+            dm += E1[K + l] * xm[l];
+            dp += E0[K + l] * xp[l];
+          }
+          F[cc][2 * fld][f] = xm[K - 1] - xp[0];
+          F[cc][2 * fld + 1][f] = T(0.5) * (dm + dp);
         }
-        g[k2] = s2;
       }
-      const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
-      dk[a.seg[2] + (int64_t)fi * NF + f] =
-          (a.terms & 2) ? wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]) : T(0);
+      sync();
+      if (has) {
+        T g[4];
+        const int q0 = f % K, q1 = f / K;
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+          T s2 = 0;
+          if constexpr (D == 3) {
+#pragma unroll
+            for (int b = 0; b < K; ++b) {
+              T s1 = 0;
+#pragma unroll
+              for (int a2 = 0; a2 < K; ++a2) s1 += S[q0 * K + a2] * F[cc][k2][a2 + K * b];
+              s2 += S[q1 * K + b] * s1;
+            }
+          } else {
+#pragma unroll
+            for (int a2 = 0; a2 < K; ++a2) s2 += S[q0 * K + a2] * F[cc][k2][a2];
+          }
+          g[k2] = s2;
+        }
+        const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
+        dk[a.seg[2] + (int64_t)(first + nf_before) * NF + f] =
+            sipg ? wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]) : T(0);
+        ++nf_before;
+      }
+      sync();
     }
-    sync();
   }
 }
 
@@ -2170,7 +2212,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       if (a.n_inside > 0)
         inside_dk_kernel<K, D, T><<<grid_cap(a, (a.n_inside + CW - 1) / CW), 64, 0, s>>>(a, x, y, dk);
       if (a.n_sfaces > 0)
-        face_dk_kernel<K, D, T><<<grid_cap(a, (a.n_sfaces + CF - 1) / CF), 64, 0, s>>>(a, x, y, dk);
+        face_dk_kernel<K, D, T><<<grid_cap(a, (a.n_active + CF - 1) / CF), 64, 0, s>>>(a, x, y, dk);
       if (a.n_vbatch > 0)
         cut_dk_kernel<K, D, T, false><<<grid_cap(a, a.n_vbatch), 64, 0, s>>>(a, x, y, dk, a.vbrec, a.vdesc,
                                                                               a.n_vbatch);
