@@ -301,14 +301,27 @@ __global__ void __launch_bounds__(256) gather_kernel(int64_t n_cell, const int32
 }
 
 // every node sums its cells' contributions in the fixed order of node_src
-// (no atomics: repeated applies are bit-identical)
+// (no atomics: repeated applies are bit-identical).  A lattice node lies in
+// at most 2^3 cells: all its source indices are loaded at once, then all
+// values, so that a node costs two dependent memory round trips.
+constexpr int kMaxNodeCells = 8;
 template <typename T>
 __global__ void __launch_bounds__(256) scatter_kernel(int64_t n_nodes, const int64_t* __restrict__ node_ptr,
                                                       const int32_t* __restrict__ node_src,
                                                       const T* __restrict__ vcell, T* __restrict__ v) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_nodes; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = node_ptr[j];
+    const int n = (int)(node_ptr[j + 1] - b);
+    int src[kMaxNodeCells];
+#pragma unroll
+    for (int k = 0; k < kMaxNodeCells; ++k) src[k] = k < n ? node_src[b + k] : 0;
+    T val[kMaxNodeCells];
+#pragma unroll
+    for (int k = 0; k < kMaxNodeCells; ++k) val[k] = k < n ? vcell[src[k]] : T(0);
     T s = 0;
-    for (int64_t k = node_ptr[j]; k < node_ptr[j + 1]; ++k) s += vcell[node_src[k]];
+#pragma unroll
+    for (int k = 0; k < kMaxNodeCells; ++k)
+      if (k < n) s += val[k];
     v[j] = s;
   }
 }

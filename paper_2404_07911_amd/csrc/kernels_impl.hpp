@@ -1773,10 +1773,13 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
       k1 = reinterpret_cast<const int4*>(a.kinfo_all)[2 * ci + 1];
       first = a.sf_first[ci];
       // the cell's DoFs of w and u: lane f loads DoFs [f K, f K + K)
+      // (without the SIPG term the face points get zeros: nothing to load)
+      if (sipg) {
 #pragma unroll
-      for (int q = 0; q < K; ++q) {
-        X[cc][0][f * K + q] = w[(int64_t)ci * ND + f * K + q];
-        X[cc][1][f * K + q] = u[(int64_t)ci * ND + f * K + q];
+        for (int q = 0; q < K; ++q) {
+          X[cc][0][f * K + q] = w[(int64_t)ci * ND + f * K + q];
+          X[cc][1][f * K + q] = u[(int64_t)ci * ND + f * K + q];
+        }
       }
     }
     const int fl = k0.y;
@@ -1786,7 +1789,7 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
       const bool has = valid && ((fl >> (kFlagStr + 2 * ax + 1)) & 1);
-      if (has) {
+      if (has && sipg) {
         const int nr = up[ax];
         const bool in_group = nr >= g0 && nr < g0 + C;
 #pragma unroll
@@ -1814,28 +1817,31 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
       }
       sync();
       if (has) {
-        T g[4];
-        const int q0 = f % K, q1 = f / K;
+        T r = 0;
+        if (sipg) {
+          T g[4];
+          const int q0 = f % K, q1 = f / K;
 #pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) {
-          T s2 = 0;
-          if constexpr (D == 3) {
+          for (int k2 = 0; k2 < 4; ++k2) {
+            T s2 = 0;
+            if constexpr (D == 3) {
 #pragma unroll
-            for (int b = 0; b < K; ++b) {
-              T s1 = 0;
+              for (int b = 0; b < K; ++b) {
+                T s1 = 0;
 #pragma unroll
-              for (int a2 = 0; a2 < K; ++a2) s1 += S[q0 * K + a2] * F[cc][k2][a2 + K * b];
-              s2 += S[q1 * K + b] * s1;
+                for (int a2 = 0; a2 < K; ++a2) s1 += S[q0 * K + a2] * F[cc][k2][a2 + K * b];
+                s2 += S[q1 * K + b] * s1;
+              }
+            } else {
+#pragma unroll
+              for (int a2 = 0; a2 < K; ++a2) s2 += S[q0 * K + a2] * F[cc][k2][a2];
             }
-          } else {
-#pragma unroll
-            for (int a2 = 0; a2 < K; ++a2) s2 += S[q0 * K + a2] * F[cc][k2][a2];
+            g[k2] = s2;
           }
-          g[k2] = s2;
+          const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
+          r = wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]);
         }
-        const T wq = a.hs * (D == 3 ? Wt[q0] * Wt[q1] : Wt[q0]);
-        dk[a.seg[2] + (int64_t)(first + nf_before) * NF + f] =
-            sipg ? wq * (-g[1] * g[2] - g[0] * g[3] + a.gamma * g[0] * g[2]) : T(0);
+        dk[a.seg[2] + (int64_t)(first + nf_before) * NF + f] = r;
         ++nf_before;
       }
       sync();
