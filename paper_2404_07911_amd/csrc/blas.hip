@@ -46,6 +46,11 @@ __global__ void __launch_bounds__(256) zero_kernel(int64_t n, T* __restrict__ y)
 }
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+// kernels that end in one atomic add per block onto one address: a grid of
+// at most 1024 blocks (four per compute unit, enough to stream the vectors
+// at full bandwidth) keeps the atomics on the one cache line few (8192 of
+// them cost more than the streaming itself)
+int grid_red(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024)); }
 
 // ------------------------------------------------- conjugate gradients
 // Device-resident CG: the scalars live in device memory, scal = [r.r, p.Ap,
@@ -132,9 +137,9 @@ hipError_t launch_cg_static_begin(int prec, int64_t n, const void* r, double* sc
   cg_clear4_kernel<<<1, 64, 0, s>>>(scal);
   if (n > 0) {
     if (prec == 0)
-      dot_kernel<double><<<grid_for(n), 256, 0, s>>>(n, (const double*)r, (const double*)r, scal);
+      dot_kernel<double><<<grid_red(n), 256, 0, s>>>(n, (const double*)r, (const double*)r, scal);
     else
-      dot_kernel<float><<<grid_for(n), 256, 0, s>>>(n, (const float*)r, (const float*)r, scal);
+      dot_kernel<float><<<grid_red(n), 256, 0, s>>>(n, (const float*)r, (const float*)r, scal);
   }
   return hipGetLastError();
 }
@@ -145,15 +150,15 @@ hipError_t launch_cg_static_end(const double* scal, double* out, hipStream_t s) 
 }
 
 hipError_t launch_cg_tail(int prec, int64_t n, void* x, void* r, void* p, const void* ap, double* scal, hipStream_t s) {
-  const int g = grid_for(n);
+  const int g = grid_for(n), gr = grid_red(n);
   if (n > 0) {
     if (prec == 0) {
-      dot_kernel<double><<<g, 256, 0, s>>>(n, (const double*)p, (const double*)ap, scal + 1);
-      cg_update_kernel<double><<<g, 256, 0, s>>>(n, (double*)r, (const double*)ap, scal);
+      dot_kernel<double><<<gr, 256, 0, s>>>(n, (const double*)p, (const double*)ap, scal + 1);
+      cg_update_kernel<double><<<gr, 256, 0, s>>>(n, (double*)r, (const double*)ap, scal);
       cg_direction_kernel<double><<<g, 256, 0, s>>>(n, (double*)x, (const double*)r, (double*)p, scal);
     } else {
-      dot_kernel<float><<<g, 256, 0, s>>>(n, (const float*)p, (const float*)ap, scal + 1);
-      cg_update_kernel<float><<<g, 256, 0, s>>>(n, (float*)r, (const float*)ap, scal);
+      dot_kernel<float><<<gr, 256, 0, s>>>(n, (const float*)p, (const float*)ap, scal + 1);
+      cg_update_kernel<float><<<gr, 256, 0, s>>>(n, (float*)r, (const float*)ap, scal);
       cg_direction_kernel<float><<<g, 256, 0, s>>>(n, (float*)x, (const float*)r, (float*)p, scal);
     }
   }
@@ -182,9 +187,9 @@ hipError_t launch_dot(int prec, int64_t n, const void* x, const void* y, double*
   zero1_kernel<<<1, 64, 0, s>>>(out);
   if (n > 0) {
     if (prec == 0)
-      dot_kernel<double><<<grid_for(n), 256, 0, s>>>(n, (const double*)x, (const double*)y, out);
+      dot_kernel<double><<<grid_red(n), 256, 0, s>>>(n, (const double*)x, (const double*)y, out);
     else
-      dot_kernel<float><<<grid_for(n), 256, 0, s>>>(n, (const float*)x, (const float*)y, out);
+      dot_kernel<float><<<grid_red(n), 256, 0, s>>>(n, (const float*)x, (const float*)y, out);
   }
   return hipGetLastError();
 }
