@@ -1849,89 +1849,39 @@ __global__ void __launch_bounds__(64) face_dk_kernel(DevArgs<T> a, const T* __re
   }
 }
 
-// cut cells: the point lines of the volume / interface (FACE = false) or of
-// the cut faces (FACE = true), with both arguments evaluated at every point
-template <int K, int D, int KA, bool FACE, typename T>
-__device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int info, int p0, int slot, const T* Wo,
-                                        const T* Wn, const T* Yo, const T* Yn, T* __restrict__ dk) {
+// cut cells: the point lines of the volume and interface rules, with both
+// arguments evaluated at every point
+template <int K, int D, int KA, typename T>
+__device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int info, int p0, const T* Wo,
+                                        const T* Yo, T* __restrict__ dk) {
   constexpr int O1 = KA == 0 ? 1 : 0;
   constexpr int O2 = KA == 2 ? 1 : 2;
   const T* Xn = tab + TabOff::X(K);
   const T* ID = tab + TabOff::ID(K);
   const int n = info & 0xffff;
-  const int kind = FACE ? 2 : ((info >> 20) & 0xf);
-  const T* px;
-  int64_t stride, kbase;
-  const T* pw;
-  const T* Eo = nullptr;
-  const T* En = nullptr;
-  int nax = -1;
-  if (FACE) {
-    const int side = slot & 1;
-    if (side == 0) return;  // the lower cell of the face writes its points
-    nax = slot >> 1;
-    Eo = tab + TabOff::E1(K);
-    En = tab + TabOff::E0(K);
-    px = a.fcut_x;
-    stride = a.n_fcut;
-    pw = a.fcut_w;
-    kbase = a.seg[3];
-  } else if (kind == 1) {
-    px = a.surf_x;
-    stride = a.n_surf;
-    pw = a.surf_w;
-    kbase = a.seg[4];
-  } else {
-    px = a.vol_x;
-    stride = a.n_vol;
-    pw = a.vol_w;
-    kbase = a.seg[1];
-  }
+  const bool surf = ((info >> 20) & 0xf) == 1;
+  const T* px = surf ? a.surf_x : a.vol_x;
+  const int64_t stride = surf ? a.n_surf : a.n_vol;
+  const T* pw = surf ? a.surf_w : a.vol_w;
+  const int64_t kbase = surf ? a.seg[4] : a.seg[1];
   // the term mask: points of a switched-off term get 0
-  const bool on = (a.terms & (FACE ? 2 : (kind == 1 ? 4 : 1))) != 0;
-  auto coord = [&](int64_t q, int ax) -> T {
-    if (FACE) {
-      const int fa = ax < nax ? ax : ax - 1;
-      return px[fa * stride + q];
-    }
-    return px[ax * stride + q];
-  };
+  const bool on = (a.terms & (surf ? 4 : 1)) != 0;
   T V1[K], dV1[K], V2[K], dV2[K];
-  T V1n[K], dV1n[K], V2n[K], dV2n[K];
-  if (FACE && O1 == nax) {
-#pragma unroll
-    for (int i = 0; i < K; ++i) { V1[i] = Eo[i]; dV1[i] = Eo[K + i]; V1n[i] = En[i]; dV1n[i] = En[K + i]; }
-  } else {
-    lagrange1d<K>(Xn, ID, coord(p0, O1), V1, dV1);
-#pragma unroll
-    for (int i = 0; i < K; ++i) { V1n[i] = V1[i]; dV1n[i] = dV1[i]; }
-  }
+  lagrange1d<K>(Xn, ID, px[O1 * stride + p0], V1, dV1);
   if constexpr (D == 3) {
-    if (FACE && O2 == nax) {
-#pragma unroll
-      for (int i = 0; i < K; ++i) { V2[i] = Eo[i]; dV2[i] = Eo[K + i]; V2n[i] = En[i]; dV2n[i] = En[K + i]; }
-    } else {
-      lagrange1d<K>(Xn, ID, coord(p0, O2), V2, dV2);
-#pragma unroll
-      for (int i = 0; i < K; ++i) { V2n[i] = V2[i]; dV2n[i] = dV2[i]; }
-    }
+    lagrange1d<K>(Xn, ID, px[O2 * stride + p0], V2, dV2);
   } else {
 #pragma unroll
-    for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; V2n[i] = 1; dV2n[i] = 0; }
+    for (int i = 0; i < K; ++i) { V2[i] = 1; dV2[i] = 0; }
   }
-  // columns: [field][own/neighbour][value, d_o1, d_o2][K]
+  // columns of w and u: [value, d_o1, d_o2][K]
   T cw[3][K], cu[3][K];
   line_columns<K, D, KA>(Wo, V1, dV1, V2, dV2, cw[0], cw[1], cw[2]);
   line_columns<K, D, KA>(Yo, V1, dV1, V2, dV2, cu[0], cu[1], cu[2]);
-  T nw[3][K], nu[3][K];
-  if constexpr (FACE) {
-    line_columns<K, D, KA>(Wn, V1n, dV1n, V2n, dV2n, nw[0], nw[1], nw[2]);
-    line_columns<K, D, KA>(Yn, V1n, dV1n, V2n, dV2n, nu[0], nu[1], nu[2]);
-  }
   for (int pi = 0; pi < n; ++pi) {
     const int64_t q = p0 + pi;
     T Z[K], dZ[K];
-    lagrange1d<K>(Xn, ID, coord(q, KA), Z, dZ);
+    lagrange1d<K>(Xn, ID, px[KA * stride + q], Z, dZ);
     T ew[4] = {0, 0, 0, 0}, eu[4] = {0, 0, 0, 0};  // value, d_k, d_o1, d_o2
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -1946,22 +1896,7 @@ __device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int i
     }
     const T c = a.hs * pw[q];
     T val;
-    if constexpr (FACE) {
-      T vw = 0, vu = 0, gw1 = 0, gw2 = 0, gu1 = 0, gu2 = 0;
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        vw += Z[i] * nw[0][i];
-        gw1 += Z[i] * nw[1][i];
-        gw2 += Z[i] * nw[2][i];
-        vu += Z[i] * nu[0][i];
-        gu1 += Z[i] * nu[1][i];
-        gu2 += Z[i] * nu[2][i];
-      }
-      const T Jw = ew[0] - vw, Ju = eu[0] - vu;
-      const T Aw = T(0.5) * ((nax == O1 ? ew[2] : ew[3]) + (nax == O1 ? gw1 : gw2));
-      const T Au = T(0.5) * ((nax == O1 ? eu[2] : eu[3]) + (nax == O1 ? gu1 : gu2));
-      val = -Aw * Ju - Jw * Au + a.gamma * Jw * Ju;
-    } else if (kind == 1) {
+    if (surf) {
       const T nk = a.surf_n[KA * stride + q], n1v = a.surf_n[O1 * stride + q];
       const T n2v = D == 3 ? a.surf_n[O2 * stride + q] : T(0);
       const T dnw = nk * ew[1] + n1v * ew[2] + n2v * ew[3];
@@ -1974,22 +1909,20 @@ __device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int i
   }
 }
 
-template <int K, int D, typename T, bool FACE>
+template <int K, int D, typename T>
 struct DkBatchWork {
-  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), FACE);
+  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false);
   T tab[TabOff::lds_size(K)];
   T Wo[ME][ND];
   T Yo[ME][ND];
-  T Wn[FACE ? ME : 1][FACE ? ND : 1];
-  T Yn[FACE ? ME : 1][FACE ? ND : 1];
   int rec[batch_record_ints(ME)];
 };
 
-template <int K, int D, typename T, bool FACE>
+template <int K, int D, typename T>
 __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __restrict__ w, const T* __restrict__ u,
                                                     T* __restrict__ dk, const int32_t* __restrict__ brec,
                                                     const int32_t* __restrict__ desc, int n_batches) {
-  using BW = DkBatchWork<K, D, T, FACE>;
+  using BW = DkBatchWork<K, D, T>;
   constexpr int ND = BW::ND, ME = BW::ME, NT = 64, NR = batch_record_ints(ME);
   __shared__ BW W;
   for (int i = threadIdx.x; i < TabOff::lds_size(K); i += NT) W.tab[i] = a.tab[i];
@@ -2004,28 +1937,16 @@ __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __res
       const int64_t ro = (int64_t)ent[4 * e] * ND + l;
       W.Wo[e][l] = w[ro];
       W.Yo[e][l] = u[ro];
-      if constexpr (FACE) {
-        const int64_t rn = (int64_t)ent[4 * e + 3] * ND + l;
-        W.Wn[e][l] = w[rn];
-        W.Yn[e][l] = u[rn];
-      }
     }
     sync();
     for (int g = t; g < total; g += NT) {
       const int2 hd = g < kBatchLines ? *reinterpret_cast<const int2*>(desc + 2 * ((int64_t)b * kBatchLines + g))
                                       : batch_desc(desc, n_batches, ovf, g);
       const int info = hd.y & 0xffffff, e = hd.y >> 24;
-      int ax = (info >> 16) & 0xf;
-      const int s = ent[4 * e + 2] >> kBatchOffsetBits;
-      if constexpr (FACE) {
-        const int nax = s >> 1;
-        ax = ax < nax ? ax : ax + 1;
-      }
-      const T* Wn = FACE ? &W.Wn[e][0] : nullptr;
-      const T* Yn = FACE ? &W.Yn[e][0] : nullptr;
-      if (ax == 0) line_dk<K, D, 0, FACE>(W.tab, a, info, hd.x, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
-      else if (ax == 1 || D == 2) line_dk<K, D, 1, FACE>(W.tab, a, info, hd.x, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
-      else if constexpr (D == 3) line_dk<K, D, 2, FACE>(W.tab, a, info, hd.x, s, W.Wo[e], Wn, W.Yo[e], Yn, dk);
+      const int ax = (info >> 16) & 0xf;
+      if (ax == 0) line_dk<K, D, 0>(W.tab, a, info, hd.x, W.Wo[e], W.Yo[e], dk);
+      else if (ax == 1 || D == 2) line_dk<K, D, 1>(W.tab, a, info, hd.x, W.Wo[e], W.Yo[e], dk);
+      else if constexpr (D == 3) line_dk<K, D, 2>(W.tab, a, info, hd.x, W.Wo[e], W.Yo[e], dk);
     }
     sync();
   }
@@ -2220,7 +2141,7 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       if (a.n_sfaces > 0)
         face_dk_kernel<K, D, T><<<grid_cap(a, (a.n_active + CF - 1) / CF), 64, 0, s>>>(a, x, y, dk);
       if (a.n_vbatch > 0)
-        cut_dk_kernel<K, D, T, false><<<grid_cap(a, a.n_vbatch), 64, 0, s>>>(a, x, y, dk, a.vbrec, a.vdesc,
+        cut_dk_kernel<K, D, T><<<grid_cap(a, a.n_vbatch), 64, 0, s>>>(a, x, y, dk, a.vbrec, a.vdesc,
                                                                               a.n_vbatch);
       if (a.n_fbatch > 0)
         cut_face_dk_kernel<K, D, T><<<grid_cap(a, a.n_fbatch), 64, 0, s>>>(a, x, y, dk, a.fbrec, a.fdesc,
