@@ -47,21 +47,46 @@ __device__ __forceinline__ int xcd_block() {
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// 1D GLL Lagrange values and first derivatives at t
+// 1D GLL Lagrange values and first derivatives at t: L_i = ID_i prod_{j != i}
+// (t - X_j).  Up to K = 4 each i takes its own product (K independent
+// chains); from K = 5 on the products over j < i and j > i are formed once
+// as prefix and suffix products with their derivatives (about 10 K instead
+// of 2 K^2 operations: 76 against 136 at K = 8).
 template <int K, typename T>
 __device__ __forceinline__ void lagrange1d(const T* __restrict__ X, const T* __restrict__ ID, T t, T* L, T* dL) {
+  if constexpr (K <= 4) {
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    T prod = 1, dsum = 0;
+    for (int i = 0; i < K; ++i) {
+      T prod = 1, dsum = 0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      if (j == i) continue;
-      const T f = t - X[j];
-      dsum = dsum * f + prod;
-      prod = prod * f;
+      for (int j = 0; j < K; ++j) {
+        if (j == i) continue;
+        const T f = t - X[j];
+        dsum = dsum * f + prod;
+        prod = prod * f;
+      }
+      L[i] = prod * ID[i];
+      dL[i] = dsum * ID[i];
     }
-    L[i] = prod * ID[i];
-    dL[i] = dsum * ID[i];
+  } else {
+    T f[K], P[K], dP[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) f[j] = t - X[j];
+    P[0] = 1;
+    dP[0] = 0;
+#pragma unroll
+    for (int i = 1; i < K; ++i) {
+      dP[i] = dP[i - 1] * f[i - 1] + P[i - 1];
+      P[i] = P[i - 1] * f[i - 1];
+    }
+    T S = 1, dS = 0;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+      L[i] = P[i] * S * ID[i];
+      dL[i] = (dP[i] * S + P[i] * dS) * ID[i];
+      dS = dS * f[i] + S;
+      S = S * f[i];
+    }
   }
 }
 
