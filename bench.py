@@ -317,7 +317,7 @@ def run_solve(op, plan, rng, tol, inner_rtol):
     import torch
 
     import ufem_inputs as ui
-    from paper_2404_07911_amd.solvers import DeviceOps, device_cg, device_defect_correction, timed
+    from paper_2404_07911_amd.solvers import DeviceOps, device_cg, device_defect_correction, device_reliable_cg, timed
 
     ops = DeviceOps(0)
     n = plan.info["n_dofs"]
@@ -339,6 +339,10 @@ def run_solve(op, plan, rng, tol, inner_rtol):
     (u, idc), tdc = timed(lambda: device_defect_correction(op, b, tol=tol, inner_rtol=inner_rtol, progress=tick), ops)
     r = op.apply(u)
     resdc = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
+    progress(f"solve: defect correction done ({idc['inner_iterations']} inner iterations, {tdc:.1f} s); "
+             "FP32 CG with reliable updates")
+    (u2, irl), trl = timed(lambda: device_reliable_cg(op, b, tol=tol, progress=tick), ops)
+    resrl = float(torch.linalg.norm(b - op.apply(u2)) / torch.linalg.norm(b))
     err = float(torch.linalg.norm(u - ustar) / torch.linalg.norm(ustar))
     w = (r - b).contiguous()
     atw = torch.empty_like(w)
@@ -351,6 +355,9 @@ def run_solve(op, plan, rng, tol, inner_rtol):
                     "converged": i64["converged"]},
         "defect_correction": {"seconds": tdc, "outer": idc["outer"], "inner_iterations": idc["inner_iterations"],
                               "rel_residual": resdc, "converged": idc["converged"], "inner_rtol": inner_rtol},
+        "reliable_update_cg": {"seconds": trl, "fp32_iterations": irl["iterations"], "updates": irl["updates"],
+                               "rel_residual": resrl, "converged": irl["converged"],
+                               "speedup_over_fp64": t64 / trl},
         "solution_rel_error": err,
         "adjoint_at_solution_s": tadj,
     }

@@ -302,6 +302,83 @@ def device_defect_correction(op, b, tol=1e-10, inner_rtol=1e-4, max_outer=60, ma
     return u, info
 
 
+def device_reliable_cg(op, b, tol=1e-10, delta=0.1, maxiter=400000, chunk=32, progress=None):
+    """CG with its iterations in FP32 on the device (`ufem_cg_iterate`) and
+    reliable updates in FP64: the FP32 iterate y is a correction to the FP64
+    solution u of A u = b (b: float64 device tensor).  Whenever the FP32
+    recursive residual has dropped by `delta` since the last update (or its
+    estimate reaches tol ||b||), u += s y in FP64, the true residual
+    r = b - A u is formed with the FP64 apply and replaces the FP32 residual
+    (scaled to unit norm, s = ||r||), y restarts from zero and the search
+    direction p is kept, rescaled to the new unit: unlike a restarted defect
+    correction, the FP32 iterations go on in the Krylov space built so far.
+    Converged when an update finds ||b - A u|| <= tol ||b|| (FP64).
+    Returns (u, info): FP32 iterations, updates, FP64 relative residual."""
+    import torch
+
+    ops = DeviceOps(b.device.index or 0)
+    stream = ops._stream()
+    n = b.numel()
+    u = torch.zeros_like(b)
+    r = b.clone()
+    bnorm = math.sqrt(ops.dot(b, b))
+    info = {"iterations": 0, "updates": 0, "converged": False, "breakdown": False, "rel_residual": None}
+    if bnorm == 0.0:
+        info.update(converged=True, rel_residual=0.0)
+        return u, info
+    s = bnorm
+    r32 = torch.empty(n, dtype=torch.float32, device=b.device)
+    ops.copy(r32, r)
+    ops.axpby(0.0, r32, 1.0 / s, r32)  # r32 = r / s
+    p32 = r32.clone()
+    y32 = torch.zeros_like(r32)
+    ap32 = torch.empty_like(r32)
+    y64 = torch.empty_like(b)
+    scal = torch.zeros(4, dtype=torch.float64, device=b.device)
+
+    def set_rr():
+        L.check(L.lib().ufem_dot(L.F32, n, C.c_void_p(r32.data_ptr()), C.c_void_p(r32.data_ptr()),
+                                 C.c_void_p(scal.data_ptr()), stream))
+
+    set_rr()
+    it = 0
+    res = 1.0
+    while it < maxiter:
+        k = min(chunk, maxiter - it)
+        L.check(L.lib().ufem_cg_iterate(op._h, L.F32, k, C.c_void_p(y32.data_ptr()), C.c_void_p(r32.data_ptr()),
+                                        C.c_void_p(p32.data_ptr()), C.c_void_p(ap32.data_ptr()),
+                                        C.c_void_p(scal.data_ptr()), stream))
+        it += k
+        sc = scal.cpu()
+        rr = max(float(sc[0]), 0.0)
+        if sc[3] != 0.0:
+            info["breakdown"] = True
+        if rr > delta * delta and s * math.sqrt(rr) > tol * bnorm and not info["breakdown"] and it < maxiter:
+            continue
+        # reliable update: u += s y, r = b - A u in FP64
+        ops.copy(y64, y32)
+        ops.axpby(s, y64, 1.0, u)
+        y32.zero_()
+        op.apply(u, r)
+        ops.axpby(1.0, b, -1.0, r)
+        rn = math.sqrt(ops.dot(r, r))
+        info["updates"] += 1
+        res = rn / bnorm
+        if progress is not None:
+            progress(it, res)
+        if rn <= tol * bnorm or info["breakdown"] or rn == 0.0:
+            break
+        ops.copy(r32, r)
+        ops.axpby(0.0, r32, 1.0 / rn, r32)  # r32 = r / rn
+        ops.axpby(0.0, p32, s / rn, p32)    # p in the new unit
+        s = rn
+        set_rr()
+    info["iterations"] = it
+    info["rel_residual"] = res
+    info["converged"] = res <= tol
+    return u, info
+
+
 def timed(fn, ops):
     ops.sync()
     t0 = time.perf_counter()

@@ -91,6 +91,27 @@ def test_device_cg_and_defect_correction(torch, ball):
     assert res < 2e-10, res
 
 
+def test_device_reliable_update_cg(torch, ball):
+    """FP32 CG iterations with FP64 reliable updates reach 1e-10, checked with
+    the oracle; the updates replace the FP32 residual several times (each
+    after a reduction by delta), and the FP32 iterations stay within a small
+    factor of the FP64 CG's."""
+    from paper_2404_07911_amd.solvers import device_cg, device_reliable_cg
+
+    wl, ora, op, ustar = ball
+    us = torch.from_numpy(ustar).cuda()
+    b = op.apply(us)
+    bh = b.cpu().numpy()
+    _say("[solve] device reliable-update cg")
+    u, info = device_reliable_cg(op, b, tol=1e-10, delta=0.1, chunk=16)
+    assert info["converged"] and not info["breakdown"], info
+    assert info["updates"] >= 5, info
+    res = np.linalg.norm(bh - ora.apply(u.cpu().numpy())) / np.linalg.norm(bh)
+    assert res < 2e-10, res
+    x, i64 = device_cg(op, b, torch.zeros_like(b), rtol=1e-10, maxiter=20000, chunk=16)
+    assert info["iterations"] <= 2 * i64["iterations"] + 64, (info, i64)
+
+
 def test_device_cg_breakdown_flag(torch, ball):
     """A right-hand side of zero leaves x at zero (converged at once); an
     operator that is not positive definite along p raises the breakdown flag:
