@@ -1,6 +1,8 @@
-"""Iterative solvers around the operator: conjugate gradients and the
+"""Iterative solvers around the operator: conjugate gradients, the
 mixed-precision defect correction (FP32 inner solves, FP64 residual and
-update), written once against a small vector-operations interface.
+update) and FP32 CG with FP64 reliable updates (residual replacement),
+written against a small vector-operations interface or the device CG of
+libufem.
 
 The paper solves with a preconditioned CG (Section 3.6); the
 preconditioners it uses live in external libraries and are not part of
