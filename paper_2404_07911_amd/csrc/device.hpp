@@ -49,12 +49,14 @@ constexpr int kFlagNoVolume = 24;
 // in one batch.
 // entries (one per cell, or per cut face of a cell) and cells of a batch (a
 // cut cell has at least 2 k^(d-1) volume and interface lines, so a batch of
-// 64 lines rarely holds more volume entries than these)
+// 64 lines rarely holds more volume entries than these; at degree 1 a cut
+// cell has about 4 cut faces with 10 face lines in all, so that 6 cells
+// fill a round of face lines)
 constexpr __host__ __device__ int batch_max_entries(int nd, bool face) {
-  return face ? (nd <= 64 ? 12 : 6) : (nd <= 27 ? 8 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1)));
+  return face ? (nd <= 8 ? 24 : (nd <= 64 ? 12 : 6)) : (nd <= 27 ? 8 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1)));
 }
 constexpr __host__ __device__ int batch_max_cells(int nd, bool face) {
-  return face ? (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1)) : batch_max_entries(nd, false);
+  return face ? (nd <= 8 ? 6 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1))) : batch_max_entries(nd, false);
 }
 constexpr __host__ __device__ int batch_record_ints(int me) { return 4 + 4 * me; }
 constexpr int kBatchLines = 64;        // lines per round (one per lane)

@@ -1077,7 +1077,7 @@ __device__ __forceinline__ void batch_acc_store(T* __restrict__ v, const int* ra
 // the batch record (header and entries, batch_record_ints(ME) ints at a
 // fixed stride) and the lane's first-round line descriptor
 struct BatchFetch {
-  int rec;
+  int2 rec;  // record ints 2t, 2t + 1 (records hold at most 2 kBatchLines ints)
   int2 hd;
 };
 
@@ -1085,10 +1085,11 @@ template <int ME>
 __device__ __forceinline__ BatchFetch batch_fetch(const int32_t* __restrict__ brec, const int32_t* __restrict__ desc,
                                                   int b, int n_batches) {
   constexpr int NR = batch_record_ints(ME);
-  BatchFetch f{0, make_int2(0, 0)};
+  static_assert(NR % 2 == 0 && NR <= 2 * kBatchLines, "batch records are fetched as int pairs");
+  BatchFetch f{make_int2(0, 0), make_int2(0, 0)};
   if (b < n_batches) {
     const int t = threadIdx.x;
-    if (t < NR) f.rec = brec[(int64_t)b * NR + t];
+    if (2 * t < NR) f.rec = *reinterpret_cast<const int2*>(brec + (int64_t)b * NR + 2 * t);
     f.hd = *reinterpret_cast<const int2*>(desc + 2 * ((int64_t)b * kBatchLines + t));
   }
   return f;
@@ -1230,7 +1231,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 5 
   BatchFetch nxt = batch_fetch<ME>(brec, desc, blockIdx.x, n_batches);
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     const BatchFetch cur = nxt;
-    if (t < NR) W.rec[t] = cur.rec;
+    if (2 * t < NR) {
+      W.rec[2 * t] = cur.rec.x;
+      W.rec[2 * t + 1] = cur.rec.y;
+    }
     sync();
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
@@ -1435,10 +1439,11 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
 
 // (double, K >= 7: two waves per SIMD with a few spilled registers beat one
 // wave, 18 % at K = 7 measured; float, K = 4: five waves instead of four,
-// 6 % measured)
+// 6 % measured; K = 2: four waves with the batches of up to 6 cells, 7 %
+// measured in double)
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K >= 7 ? 2 : (sizeof(T) == 4 && K == 4 ? 5 : 1))))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K >= 7 ? 2 : (sizeof(T) == 4 && K == 4 ? 5 : (K == 2 ? 4 : 1)))))
 cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                       const int32_t* __restrict__ brec,
                                                       const int32_t* __restrict__ desc, int n_batches) {
@@ -1456,7 +1461,10 @@ cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
   BatchFetch nxt = batch_fetch<ME>(brec, desc, blockIdx.x, n_batches);
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     const BatchFetch cur = nxt;
-    if (t < NR) W.rec[t] = cur.rec;
+    if (2 * t < NR) {
+      W.rec[2 * t] = cur.rec.x;
+      W.rec[2 * t + 1] = cur.rec.y;
+    }
     sync();
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
@@ -1953,7 +1961,7 @@ __global__ void __launch_bounds__(64) cut_dk_kernel(DevArgs<T> a, const T* __res
   for (int i = threadIdx.x; i < TabOff::lds_size(K); i += NT) W.tab[i] = a.tab[i];
   const int t = threadIdx.x;
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
-    if (t < NR) W.rec[t] = brec[(int64_t)b * NR + t];
+    for (int i = t; i < NR; i += NT) W.rec[i] = brec[(int64_t)b * NR + i];
     sync();
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
     const int* ent = W.rec + 4;
@@ -2003,7 +2011,7 @@ cut_face_dk_kernel(DevArgs<T> a, const T* __restrict__ w,
   const T* ID = tab + TabOff::ID(K);
   const int t = threadIdx.x;
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
-    if (t < NR) W.rec[t] = brec[(int64_t)b * NR + t];
+    for (int i = t; i < NR; i += NT) W.rec[i] = brec[(int64_t)b * NR + i];
     sync();
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
     const int* ent = W.rec + 4;
