@@ -713,27 +713,29 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 
           // FJ[j] = E^j u_own - F^j u_nb; volume kind: the line of the patch
           // mass products, FJ[j] = (Go u_own - Gn u_nb)[j] (the in-face mass
           // of the patch integral is the face transform below)
-          const T* Go = tab + TabOff::GP(K) + 2 * side * K * K;
-          const T* Gn = Go + K * K;
+          // (the two kinds in separate loops: a select inside one loop keeps
+          // both tables' products live and costs registers)
           const bool vgp = a.gp_volume != 0;
           if (fg) {
+            const T* Fo = vgp ? tab + TabOff::GP(K) + 2 * side * K * K : Eo;
+            const T* Fn = vgp ? Fo + K * K : En;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
               T dj = 0;
 #pragma unroll
-              for (int q = 0; q < K; ++q)
-                dj += vgp ? Go[j * K + q] * uo[q] - Gn[j * K + q] * un[q] : Eo[j * K + q] * uo[q] - En[j * K + q] * un[q];
+              for (int q = 0; q < K; ++q) dj += Fo[j * K + q] * uo[q] - Fn[j * K + q] * un[q];
               W.FJ[cc][j][l] = dj;
             }
           }
           sync();
           if (fg) {
+            if (vgp) {
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-              const T g = a.hs * face_transform<K, D, false>(M, W.FJ[cc][j], l);
-              if (vgp) {
-                R[j] += g;
-              } else {
+              for (int j = 0; j < K; ++j) R[j] += a.hs * face_transform<K, D, false>(M, W.FJ[cc][j], l);
+            } else {
+#pragma unroll
+              for (int j = 0; j < K; ++j) {
+                const T g = a.hs * face_transform<K, D, false>(M, W.FJ[cc][j], l);
 #pragma unroll
                 for (int q = 0; q < K; ++q) R[q] += Eo[j * K + q] * (GW[j] * g);
               }
