@@ -51,9 +51,10 @@ constexpr int kFlagNoVolume = 24;
 // cut cell has at least 2 k^(d-1) volume and interface lines, so a batch of
 // 64 lines rarely holds more volume entries than these; at degree 1 a cut
 // cell has about 4 cut faces with 10 face lines in all, so that 6 cells
-// fill a round of face lines)
+// fill a round of face lines; a 3D cut cell at degree 4 has at least 50
+// lines, so its batches hold one cell)
 constexpr __host__ __device__ int batch_max_entries(int nd, bool face) {
-  return face ? (nd <= 8 ? 24 : (nd <= 64 ? 12 : 6)) : (nd <= 27 ? 8 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1)));
+  return face ? (nd <= 8 ? 24 : (nd <= 64 ? 12 : 6)) : (nd <= 27 ? 8 : (nd <= 64 ? 4 : (nd < 125 ? 2 : 1)));
 }
 constexpr __host__ __device__ int batch_max_cells(int nd, bool face) {
   return face ? (nd <= 8 ? 6 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1))) : batch_max_entries(nd, false);

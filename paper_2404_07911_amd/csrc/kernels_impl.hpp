@@ -824,8 +824,10 @@ struct LineShape {
                        D1 = D0 + K, D2 = D0 + 2 * K;
   // records are stored one after the other with this stride (= 2 mod 4
   // elements: 16-byte aligned records whose pair accesses by consecutive
-  // lanes fall into distinct bank groups)
-  static constexpr int RSP = RS + ((2 - RS % 4) + 4) % 4;
+  // lanes fall into distinct bank groups); at K = 5 in 3D without padding,
+  // so that a batch's LDS (one cell, 64 records) stays under 20 KiB and two
+  // waves fit per SIMD (volume lines 209 -> 166 us at p = 4, 2e7 DoF)
+  static constexpr int RSP = (K == 5 && D == 3) ? RS : RS + ((2 - RS % 4) + 4) % 4;
 };
 
 // columns along axis KA of the DoF tensor u contracted with (V1, dV1) over
