@@ -161,7 +161,8 @@ struct KronWork {
 };
 
 // waves per SIMD the Kronecker kernel asks the compiler for (the register
-// budget 512 / W): K = 4 in double at 5, where its three LDS tensors allow it
+// budget 512 / W; 1: no request, every request measured so far, such as five
+// waves at K = 4 in double, spilled and was slower)
 template <int K, typename T>
 struct KronOcc {
   static constexpr int W = 1;
@@ -1764,8 +1765,6 @@ __global__ void __launch_bounds__(64) inside_dk_kernel(DevArgs<T> a, const T* __
   }
 }
 
-// structured SIPG faces: traces of w and u at the Gauss-Lobatto face nodes
-// from both cells, interpolated to the face Gauss points
 // Structured SIPG faces of dL/dkappa, by groups of C consecutive active
 // cells (rank order): each cell takes its structured upper faces (slots
 // 2 ax + 1).  The group's DoFs of w and u are staged in LDS once and serve
