@@ -89,7 +89,7 @@ struct DevArgs {
   // ranks of the 2d slots, -1 padding), 8 ints
   const int32_t* kinfo_inside;
   const int32_t* kinfo_cut;
-  const int32_t* kinfo_all;  // both, in rank order, cut cells flagged kFlagNoVolume
+  const int32_t* kinfo_all;  // both, in rank order (position = active rank), cut cells flagged kFlagNoVolume
   // per position and slot: kappa offset of the structured face's points
   const int64_t* kface_inside;
   const int64_t* kface_cut;

@@ -1082,7 +1082,7 @@ __device__ __forceinline__ void batch_acc_store(T* __restrict__ v, const int* ra
 // the batch record (header and entries, batch_record_ints(ME) ints at a
 // fixed stride) and the lane's first-round line descriptor
 struct BatchFetch {
-  int2 rec;  // record ints 2t, 2t + 1 (records hold at most 2 kBatchLines ints)
+  int2 rec;  // record int t (.x), or ints 2t, 2t + 1 for records longer than kBatchLines ints
   int2 hd;
 };
 
@@ -1090,14 +1090,33 @@ template <int ME>
 __device__ __forceinline__ BatchFetch batch_fetch(const int32_t* __restrict__ brec, const int32_t* __restrict__ desc,
                                                   int b, int n_batches) {
   constexpr int NR = batch_record_ints(ME);
-  static_assert(NR % 2 == 0 && NR <= 2 * kBatchLines, "batch records are fetched as int pairs");
+  static_assert(NR % 2 == 0 && NR <= 2 * kBatchLines, "batch records are fetched as ints or int pairs");
   BatchFetch f{make_int2(0, 0), make_int2(0, 0)};
   if (b < n_batches) {
     const int t = threadIdx.x;
-    if (2 * t < NR) f.rec = *reinterpret_cast<const int2*>(brec + (int64_t)b * NR + 2 * t);
+    if constexpr (NR <= kBatchLines) {
+      if (t < NR) f.rec.x = brec[(int64_t)b * NR + t];
+    } else {
+      if (2 * t < NR) f.rec = *reinterpret_cast<const int2*>(brec + (int64_t)b * NR + 2 * t);
+    }
     f.hd = *reinterpret_cast<const int2*>(desc + 2 * ((int64_t)b * kBatchLines + t));
   }
   return f;
+}
+
+// the fetched record into LDS (rec: batch_record_ints(ME) ints)
+template <int ME>
+__device__ __forceinline__ void batch_record_store(int* rec, const BatchFetch& f) {
+  constexpr int NR = batch_record_ints(ME);
+  const int t = threadIdx.x;
+  if constexpr (NR <= kBatchLines) {
+    if (t < NR) rec[t] = f.rec.x;
+  } else {
+    if (2 * t < NR) {
+      rec[2 * t] = f.rec.x;
+      rec[2 * t + 1] = f.rec.y;
+    }
+  }
 }
 
 // line descriptor of in-batch line g >= kBatchLines
@@ -1236,10 +1255,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 5 
   BatchFetch nxt = batch_fetch<ME>(brec, desc, blockIdx.x, n_batches);
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     const BatchFetch cur = nxt;
-    if (2 * t < NR) {
-      W.rec[2 * t] = cur.rec.x;
-      W.rec[2 * t + 1] = cur.rec.y;
-    }
+    batch_record_store<ME>(W.rec, cur);
     sync();
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
@@ -1466,10 +1482,7 @@ cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
   BatchFetch nxt = batch_fetch<ME>(brec, desc, blockIdx.x, n_batches);
   for (int b = blockIdx.x; b < n_batches; b += gridDim.x) {
     const BatchFetch cur = nxt;
-    if (2 * t < NR) {
-      W.rec[2 * t] = cur.rec.x;
-      W.rec[2 * t + 1] = cur.rec.y;
-    }
+    batch_record_store<ME>(W.rec, cur);
     sync();
     nxt = batch_fetch<ME>(brec, desc, b + gridDim.x, n_batches);
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
