@@ -188,9 +188,12 @@ struct ufem_op {
   // integer data
   int32_t* inside = nullptr;
   int64_t *kface_inside = nullptr, *kface_cut = nullptr;
-  int32_t *vbrec = nullptr, *vdesc = nullptr, *fbrec = nullptr, *fdesc = nullptr, *kinfo_inside = nullptr,
+  // volume batches per precision (index 0: double, 1: float; the same
+  // arrays when both precisions take the same batch size)
+  int32_t *vbrec[2] = {nullptr, nullptr}, *vdesc[2] = {nullptr, nullptr};
+  int32_t *fbrec = nullptr, *fdesc = nullptr, *kinfo_inside = nullptr,
           *kinfo_cut = nullptr, *kinfo_all = nullptr, *sf_first = nullptr;
-  int32_t n_vbatch = 0, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
+  int32_t n_vbatch[2] = {0, 0}, n_fbatch = 0, n_sfaces = 0, n_cu = 1;
   int32_t* cut_rank = nullptr;      // active ranks of the cut cells
   // continuous space: P (cell DoF -> node), P^T (node -> its cell DoFs) and
   // three cell-layout vectors (float64 size, shared by both precisions)
@@ -279,12 +282,13 @@ ufem::DevArgs<T> ufem_op::args(const Prec& d) const {
   a.kinfo_all = kinfo_all;
   a.kface_inside = kface_inside;
   a.kface_cut = kface_cut;
-  a.vbrec = vbrec;
-  a.vdesc = vdesc;
+  const int vp = sizeof(T) == 4 ? 1 : 0;
+  a.vbrec = vbrec[vp];
+  a.vdesc = vdesc[vp];
   a.fbrec = fbrec;
   a.fdesc = fdesc;
   a.n_cu = n_cu;
-  a.n_vbatch = n_vbatch;
+  a.n_vbatch = n_vbatch[vp];
   a.n_fbatch = n_fbatch;
   a.sf_first = sf_first;
   a.n_sfaces = n_sfaces;
@@ -550,9 +554,10 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
     // its own.  Fixed-size batch records and line descriptors (layout in
     // device.hpp), the lines of each entry ordered by axis.
     bool batch_overflow = false;
-    auto make_batches = [&](bool face, std::vector<int32_t>& brec, std::vector<int32_t>& desc, int32_t& n_batches) {
-      const int me = ufem::batch_max_entries((int)P.nd(), face);
-      const int mc = ufem::batch_max_cells((int)P.nd(), face);
+    auto make_batches = [&](bool face, bool f32, std::vector<int32_t>& brec, std::vector<int32_t>& desc,
+                            int32_t& n_batches) {
+      const int me = ufem::batch_max_entries((int)P.nd(), face, f32);
+      const int mc = ufem::batch_max_cells((int)P.nd(), face, f32);
       const int nr = ufem::batch_record_ints(me);
       std::vector<int32_t> rec, lines, ovf;  // current batch; overflow area
       int cur_n = 0, cur_cells = 0;
@@ -684,9 +689,11 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         ++i;
       }
     }
-    std::vector<int32_t> vb, vl, fb, fl;
-    make_batches(false, vb, vl, op->n_vbatch);
-    make_batches(true, fb, fl, op->n_fbatch);
+    std::vector<int32_t> vb, vl, vb32, vl32, fb, fl;
+    make_batches(false, false, vb, vl, op->n_vbatch[0]);
+    const bool own32 = ufem::batch_max_entries((int)P.nd(), false, true) != ufem::batch_max_entries((int)P.nd(), false);
+    if (own32) make_batches(false, true, vb32, vl32, op->n_vbatch[1]);
+    make_batches(true, false, fb, fl, op->n_fbatch);
 
     if (batch_overflow) {
       delete op;
@@ -697,11 +704,17 @@ int ufem_setup(const ufem_plan* plan, int device, void* stream, int64_t max_devi
         (rc = op->upload((void**)&op->kinfo_inside, kin)) || (rc = op->upload((void**)&op->kinfo_cut, kcu)) ||
         (rc = op->upload((void**)&op->kinfo_all, kall)) || (rc = op->upload((void**)&op->kface_inside, kfin)) ||
         (rc = op->upload((void**)&op->kface_cut, kfcu)) ||
-        (rc = op->upload((void**)&op->vbrec, vb)) || (rc = op->upload((void**)&op->vdesc, vl)) ||
+        (rc = op->upload((void**)&op->vbrec[0], vb)) || (rc = op->upload((void**)&op->vdesc[0], vl)) ||
+        (own32 && ((rc = op->upload((void**)&op->vbrec[1], vb32)) || (rc = op->upload((void**)&op->vdesc[1], vl32)))) ||
         (rc = op->upload((void**)&op->fbrec, fb)) || (rc = op->upload((void**)&op->fdesc, fl)) ||
         (rc = op->upload((void**)&op->sf_first, sff))) {
       delete op;
       return rc;
+    }
+    if (!own32) {
+      op->vbrec[1] = op->vbrec[0];
+      op->vdesc[1] = op->vdesc[0];
+      op->n_vbatch[1] = op->n_vbatch[0];
     }
     if (P.cg) {
       std::vector<int32_t> src(P.node_src.begin(), P.node_src.end());

@@ -53,11 +53,17 @@ constexpr int kFlagNoVolume = 24;
 // cell has about 4 cut faces with 10 face lines in all, so that 6 cells
 // fill a round of face lines; a 3D cut cell at degree 4 has at least 50
 // lines, so its batches hold one cell)
-constexpr __host__ __device__ int batch_max_entries(int nd, bool face) {
-  return face ? (nd <= 8 ? 24 : (nd <= 64 ? 12 : 6)) : (nd <= 27 ? 8 : (nd <= 64 ? 4 : (nd < 125 ? 2 : 1)));
+// Volume batches depend on the precision (f32): at K^d = 64 the float
+// kernel takes two cells per batch, whose smaller LDS allows four waves per
+// SIMD (float volume lines 38.9 -> 35.6 us at 64^3, p = 3; 178 -> 142 us for
+// 20 balls at 128^3), while the double kernel, held at two waves by its
+// registers, keeps four (fewer batches).
+constexpr __host__ __device__ int batch_max_entries(int nd, bool face, bool f32 = false) {
+  return face ? (nd <= 8 ? 24 : (nd <= 64 ? 12 : 6))
+              : (nd <= 27 ? 8 : (nd <= 64 ? (f32 ? 2 : 4) : (nd < 125 ? 2 : 1)));
 }
-constexpr __host__ __device__ int batch_max_cells(int nd, bool face) {
-  return face ? (nd <= 8 ? 6 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1))) : batch_max_entries(nd, false);
+constexpr __host__ __device__ int batch_max_cells(int nd, bool face, bool f32 = false) {
+  return face ? (nd <= 8 ? 6 : (nd <= 64 ? 4 : (nd <= 125 ? 2 : 1))) : batch_max_entries(nd, false, f32);
 }
 constexpr __host__ __device__ int batch_record_ints(int me) { return 4 + 4 * me; }
 constexpr int kBatchLines = 64;        // lines per round (one per lane)

@@ -1152,7 +1152,7 @@ struct ReduceShape {
 
 template <int K, int D, typename T>
 struct BatchWork {
-  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false),
+  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false, sizeof(T) == 4),
                        RS = LineShape<K, D>::RS, RP = BatchShape<K, D>::RP;
   T U[ME][ND];
   double OUT[ME][ND];  // the cells' rows of v (double also for T = float)
@@ -1960,7 +1960,7 @@ __device__ __forceinline__ void line_dk(const T* tab, const DevArgs<T>& a, int i
 
 template <int K, int D, typename T>
 struct DkBatchWork {
-  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false);
+  static constexpr int ND = BatchShape<K, D>::ND, ME = batch_max_entries(ipow(K, D), false, sizeof(T) == 4);
   T tab[TabOff::lds_size(K)];
   T Wo[ME][ND];
   T Yo[ME][ND];
