@@ -906,18 +906,26 @@ __device__ __forceinline__ void line_record_sums(const T* D0, const T* D1, const
 
 // Point data of a line, loaded ahead of the arithmetic: the two fixed
 // coordinates, and for the first PB points the coordinate along the line,
-// the weight (times kappa) and, on interface lines, the normal.
-constexpr int kLinePB = 4;
-template <typename T>
+// the weight (times kappa) and, on interface lines, the normal.  PB per
+// degree and line kind, as measured: four points, except two for the cell
+// lines at K = 2 (volume lines -10 %: the registers freed give a third
+// and fourth wave per SIMD) and K for the cut-face lines at K = 2, 3 (-3 %
+// and -4 %); K points at K = 3 cost the volume lines 25 %, and at K >= 5
+// gain at most 2 % in one precision while losing in the other.
+template <int K>
+struct LinePB {
+  static constexpr int CELL = K == 2 ? 2 : 4, FACE = K < 4 ? K : 4;
+};
+template <typename T, int PB>
 struct LinePts {
   T t1, t2;
-  T tk[kLinePB], wq[kLinePB], nk[kLinePB], n1[kLinePB], n2[kLinePB];
+  T tk[PB], wq[PB], nk[PB], n1[PB], n2[PB];
 };
 
 // loads of points [pb, pb + PB) of a volume / interface line along cell axis
 // ax (runtime) starting at point p0; fixed coordinates when pb == 0
-template <int D, typename T>
-__device__ __forceinline__ void line_load_cell(const DevArgs<T>& a, int info, int p0, int pb, LinePts<T>& L) {
+template <int D, typename T, int PB>
+__device__ __forceinline__ void line_load_cell(const DevArgs<T>& a, int info, int p0, int pb, LinePts<T, PB>& L) {
   const int n = info & 0xffff;
   const int ax = (info >> 16) & 0xf;
   const bool surf = ((info >> 20) & 0xf) == 1;
@@ -931,7 +939,7 @@ __device__ __forceinline__ void line_load_cell(const DevArgs<T>& a, int info, in
     L.t2 = D == 3 ? px[o2 * stride + p0] : T(0);
   }
 #pragma unroll
-  for (int i = 0; i < kLinePB; ++i) {
+  for (int i = 0; i < PB; ++i) {
     L.tk[i] = 0; L.wq[i] = 0; L.nk[i] = 0; L.n1[i] = 0; L.n2[i] = 0;
     if (pb + i < n) {
       const int64_t q = p0 + pb + i;
@@ -952,7 +960,8 @@ __device__ __forceinline__ void line_load_cell(const DevArgs<T>& a, int info, in
 // line; writes the line record as record r of REC.  info / p0: the line
 // descriptor (count | axis << 16 | kind << 20, first point)
 template <int K, int D, int KA, typename T>
-__device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a, int info, int p0, LinePts<T>& L,
+__device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a, int info, int p0,
+                                               LinePts<T, LinePB<K>::CELL>& L,
                                                const T* Uo, T* REC, int r) {
   const T* Xn = tab + TabOff::X(K);
   const T* ID = tab + TabOff::ID(K);
@@ -974,10 +983,10 @@ __device__ __forceinline__ void line_work_cell(const T* tab, const DevArgs<T>& a
   T D0[K], D1[K], D2[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) { D0[i] = 0; D1[i] = 0; D2[i] = 0; }
-  for (int pb = 0; pb < n; pb += kLinePB) {
+  for (int pb = 0; pb < n; pb += LinePB<K>::CELL) {
     if (pb > 0) line_load_cell<D>(a, info, p0, pb, L);
 #pragma unroll
-    for (int i = 0; i < kLinePB; ++i) {
+    for (int i = 0; i < LinePB<K>::CELL; ++i) {
       if (pb + i >= n) break;
       T Z[K], dZ[K];
       lagrange1d<K>(Xn, ID, L.tk[i], Z, dZ);
@@ -1262,7 +1271,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == 5 
     const int* ent = W.rec + 4;
     // point data of the first round, DoFs and rows of v in one round trip
     int2 hd = cur.hd;
-    LinePts<T> L;
+    LinePts<T, LinePB<K>::CELL> L;
     if (t < total) line_load_cell<D>(a, hd.y & 0xffffff, hd.x, 0, L);
     // (a loop of fixed trip count: every load is issued before the first
     // LDS store waits for one)
@@ -1364,14 +1373,14 @@ struct FaceWork {
 // point data of a cut-face line: the coordinate along the other in-face
 // axis, and for points [pb, pb + PB) the coordinate along the line and the
 // weight (times kappa)
-template <int D, typename T>
-__device__ __forceinline__ void line_load_face(const DevArgs<T>& a, int info, int p0, int pb, LinePts<T>& L) {
+template <int D, typename T, int PB>
+__device__ __forceinline__ void line_load_face(const DevArgs<T>& a, int info, int p0, int pb, LinePts<T, PB>& L) {
   const int n = info & 0xffff;
   const int fk = (info >> 16) & 0xf;  // in-face axis of the line
   const int64_t stride = a.n_fcut;
   if (pb == 0) L.t1 = D == 3 ? a.fcut_x[(1 - fk) * stride + p0] : T(0);
 #pragma unroll
-  for (int i = 0; i < kLinePB; ++i) {
+  for (int i = 0; i < PB; ++i) {
     L.tk[i] = 0; L.wq[i] = 0;
     if (pb + i < n) {
       const int64_t q = p0 + pb + i;
@@ -1386,7 +1395,8 @@ __device__ __forceinline__ void line_load_face(const DevArgs<T>& a, int info, in
 // entry's traces
 template <int K, int D, int RP, typename T>
 __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a, int info, int p0, int slot,
-                                               LinePts<T>& L, const T (*TR)[FaceShape<K, D>::NF], T* REC, int r) {
+                                               LinePts<T, LinePB<K>::FACE>& L, const T (*TR)[FaceShape<K, D>::NF], T* REC,
+                                               int r) {
   using FS = FaceShape<K, D>;
   const T* Xn = tab + TabOff::X(K);
   const T* ID = tab + TabOff::ID(K);
@@ -1422,10 +1432,10 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
   T D0[K], DN[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) { D0[i] = 0; DN[i] = 0; }
-  for (int pb = 0; pb < n; pb += kLinePB) {
+  for (int pb = 0; pb < n; pb += LinePB<K>::FACE) {
     if (pb > 0) line_load_face<D>(a, info, p0, pb, L);
 #pragma unroll
-    for (int i = 0; i < kLinePB; ++i) {
+    for (int i = 0; i < LinePB<K>::FACE; ++i) {
       if (pb + i >= n) break;
       T Z[K], dZ[K];
       lagrange1d<K>(Xn, ID, L.tk[i], Z, dZ);
@@ -1488,7 +1498,7 @@ cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
     const int ne = W.rec[0], total = W.rec[1], ovf = W.rec[2];
     const int* ent = W.rec + 4;
     int2 hd = cur.hd;
-    LinePts<T> L;
+    LinePts<T, LinePB<K>::FACE> L;
     if (t < total) line_load_face<D>(a, hd.y & 0xffffff, hd.x, 0, L);
     // traces of cell and neighbour on the face node grid (A, B); a loop of
     // fixed trip count, so that all loads are issued before the first wait
