@@ -1471,10 +1471,11 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
 // (double, K >= 7: two waves per SIMD with a few spilled registers beat one
 // wave, 18 % at K = 7 measured; float, K = 4: five waves instead of four,
 // 6 % measured; K = 2: with the batches of up to 6 cells four waves in
-// double, six in float, 7 % and 4 % measured)
+// double, six in float, 7 % and 4 % measured; K = 3: four and six, 9 % and
+// 5 % measured)
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K >= 7 ? 2 : (sizeof(T) == 4 && K == 4 ? 5 : (K == 2 ? (sizeof(T) == 8 ? 4 : 6) : 1)))))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K >= 7 ? 2 : (sizeof(T) == 4 && K == 4 ? 5 : (K <= 3 ? (sizeof(T) == 8 ? 4 : 6) : 1)))))
 cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                       const int32_t* __restrict__ brec,
                                                       const int32_t* __restrict__ desc, int n_batches) {
