@@ -161,11 +161,13 @@ struct KronWork {
 };
 
 // waves per SIMD the Kronecker kernel asks the compiler for (the register
-// budget 512 / W; 1: no request, every request measured so far, such as five
-// waves at K = 4 in double, spilled and was slower)
+// budget 512 / W; 1: no request).  Three at K = 7 in double (a few spilled
+// registers, the structured stage -11 % at p = 6); the other requests
+// measured (five at K = 4, 5, four at K = 6, three at K = 8 in double, five
+// at K = 7, 8 in float) spilled more and were slower)
 template <int K, typename T>
 struct KronOcc {
-  static constexpr int W = 1;
+  static constexpr int W = sizeof(T) == 8 && K == 7 ? 3 : 1;
 };
 
 template <int K, typename T>
@@ -1472,10 +1474,10 @@ __device__ __forceinline__ void line_work_face(const T* tab, const DevArgs<T>& a
 // wave, 18 % at K = 7 measured; float, K = 4: five waves instead of four,
 // 6 % measured; K = 2: with the batches of up to 6 cells four waves in
 // double, six in float, 7 % and 4 % measured; K = 3: four and six, 9 % and
-// 5 % measured)
+// 5 % measured; float, K = 5: four, 3 % measured)
 template <int K, int D, typename T>
 __global__ void __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K >= 7 ? 2 : (sizeof(T) == 4 && K == 4 ? 5 : (K <= 3 ? (sizeof(T) == 8 ? 4 : 6) : 1)))))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && K >= 7 ? 2 : (sizeof(T) == 4 && (K == 4 || K == 5) ? (K == 4 ? 5 : 4) : (K <= 3 ? (sizeof(T) == 8 ? 4 : 6) : 1)))))
 cut_face_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                       const int32_t* __restrict__ brec,
                                                       const int32_t* __restrict__ desc, int n_batches) {
