@@ -2179,6 +2179,19 @@ int blocks_per_cu(Kern kernel) {
   return nb;
 }
 
+// workgroups of a line kernel: one per batch (the hardware hands the next
+// batch to whichever workgroup slot frees first), or the resident ones of
+// the chip striding through the batches with the next batch's record in
+// flight.  Measured on the MI355X: one per batch is faster for the volume
+// lines from K = 4 on (-9 % in double at the 64^3 ball, -4 % / -14 % for
+// the 20 balls, -3 to -26 % at K = 5..8) and for the cut-face lines at K = 4
+// once there are more than three batches per resident workgroup (-18 % at
+// the 104^3 ball, -26 % for the 20 balls, +4 % at the 64^3 ball with under
+// two); the persistent grid is faster for the other cases (up to 11 %).
+inline int64_t line_grid(int64_t n_batches, int64_t resident, bool one_per_batch) {
+  return one_per_batch ? n_batches : std::min(n_batches, resident);
+}
+
 // workgroups of a launch: g, capped by DevArgs::max_blocks when that is set
 template <typename T>
 inline int grid_cap(const DevArgs<T>& a, int64_t g) {
@@ -2244,12 +2257,12 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
       cut_matrix_kernel<K, D, T><<<grid_cap(a, a.n_cut), 64, 0, s>>>(a, x, v);
     } else if ((a.parts & 4) && (a.terms & 5) && a.n_vbatch > 0) {
       static const int nb = blocks_per_cu(cut_batch_kernel<K, D, T>);
-      const int g = grid_cap(a, std::min(a.n_vbatch, nb * a.n_cu));
+      const int g = grid_cap(a, line_grid(a.n_vbatch, nb * a.n_cu, K >= 4));
       cut_batch_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.vbrec, a.vdesc, a.n_vbatch);
     }
     if ((a.parts & 8) && (a.terms & 2) && a.n_fbatch > 0) {
       static const int nb = blocks_per_cu(cut_face_kernel<K, D, T>);
-      const int g = grid_cap(a, std::min(a.n_fbatch, nb * a.n_cu));
+      const int g = grid_cap(a, line_grid(a.n_fbatch, nb * a.n_cu, K == 4 && a.n_fbatch > 3 * nb * a.n_cu));
       cut_face_kernel<K, D, T><<<g, 64, 0, s>>>(a, x, v, a.fbrec, a.fdesc, a.n_fbatch);
     }
   }
