@@ -271,10 +271,11 @@ def test_full_size_sampled_rows_against_stored_oracle_rows(torch, name):
 def test_multi_batch_paths(torch, name):
     """Every launch capped at 1 and at 3 workgroups: each workgroup then runs
     many cell groups of the structured kernels and many line batches of the
-    persistent cut-cell kernels (batch records and descriptors prefetched
-    across batches, LDS reused), in both precisions, for the apply, the
-    adjoint and dL/dkappa; the results equal the uncapped launches bit for
-    bit and the oracle within the tolerances."""
+    cut-cell kernels (batch records and descriptors prefetched across
+    batches, LDS reused), in both precisions, for the apply, the adjoint and
+    dL/dkappa; the results equal the uncapped launches (one workgroup per
+    batch or a persistent grid, by degree) bit for bit and the oracle within
+    the tolerances."""
     wl, ora, pl, op, u, w = _setup(name)
     ud = torch.from_numpy(u).cuda()
     wd = torch.from_numpy(w).cuda()
