@@ -116,13 +116,18 @@ __device__ __forceinline__ int cell_index(int axis, int f, int l) {
 // and ghost penalty  sum_j gamma_j E^j_l (d^j u_own - d^j u_nb)
 // (e, g, E^j: value, first and j-th derivative of the own basis at the face);
 // the in-face mass M (x) M of the face integrals is applied by the
-// subsequent passes.  One team of TS threads per cell, CPB cells per block.
+// subsequent passes.  One lane per 1D line, CK cells per workgroup.
 template <int K, int D>
 struct KronShape {
   static constexpr int ND = ipow(K, D);
   static constexpr int NL = ipow(K, D - 1);           // lines per direction
   static constexpr int C = 64 / NL;                   // cells per wave
   static constexpr int NT = 64;
+  // the Kronecker kernel's workgroup: two waves at K = 5, 6, where one wave
+  // holds 2 / 1 cells (50 / 36 of its 64 lanes busy) and two hold 5 / 3
+  // (structured stage -5 % / -20 % measured; the other degrees lose)
+  static constexpr int NTK = K == 5 || K == 6 ? 128 : 64;
+  static constexpr int CK = NTK / NL;
 };
 
 // LDS layout of a cell tensor in the Kronecker kernel: element (i0, i1, i2)
@@ -154,7 +159,7 @@ struct KronLayout {
 
 template <int K, int D, typename T>
 struct KronWork {
-  static constexpr int NDP = KronLayout<K, D>::NDP, C = KronShape<K, D>::C;
+  static constexpr int NDP = KronLayout<K, D>::NDP, C = KronShape<K, D>::CK;
   T A[C][NDP];
   T Cc[C][NDP];
   T U[C][NDP];
@@ -276,9 +281,9 @@ __device__ __forceinline__ void glb_line_load(const T* __restrict__ src, int bas
 // K^2 FMAs and K stores per lane and the 1D matrices are wave-uniform:
 //   v = hs [ M_z (M_y R_x + M_x R_y) + M_y M_x R_z ]
 template <int K, int D, typename T>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KronOcc<K, T>::W))) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
+__global__ void __launch_bounds__((KronShape<K, D>::NTK)) __attribute__((amdgpu_waves_per_eu(KronOcc<K, T>::W))) inside_kron_kernel(DevArgs<T> a, const T* __restrict__ x, T* __restrict__ v,
                                                          const int32_t* __restrict__ kinfo, int n_list, int with_volume) {
-  constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
+  constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::CK;
   __shared__ KronWork<K, D, T> W;
   const T* __restrict__ tab = a.tab;
   const T* M = tab + TabOff::M(K);
@@ -2229,11 +2234,13 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
   if (both) {
     // inside cells and the structured faces of the cut cells in one launch
     const int64_t n_all = a.n_inside + a.n_cut;
-    const int gk = grid_cap(a, (n_all + CW - 1) / CW);
-    if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_all, (int)n_all, 1);
+    constexpr int CK = KronShape<K, D>::CK;
+    const int gk = grid_cap(a, (n_all + CK - 1) / CK);
+    if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NTK, 0, s>>>(a, x, v, a.kinfo_all, (int)n_all, 1);
   } else if (a.kappa == nullptr) {
-    const int gk = (a.parts & 1) ? grid_cap(a, (a.n_inside + CW - 1) / CW) : 0;
-    if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
+    constexpr int CK = KronShape<K, D>::CK;
+    const int gk = (a.parts & 1) ? grid_cap(a, (a.n_inside + CK - 1) / CK) : 0;
+    if (gk > 0) inside_kron_kernel<K, D, T><<<gk, KronShape<K, D>::NTK, 0, s>>>(a, x, v, a.kinfo_inside, a.n_inside, 1);
   } else {
     const int gk = (a.parts & 1) ? grid_cap(a, (a.n_inside + CW - 1) / CW) : 0;
     if (gk > 0)
@@ -2248,7 +2255,8 @@ hipError_t launch_kd(const DevArgs<T>& a, const T* x, const T* y, T* v, T* dk, b
     const int gs = (a.parts & 2) && !both ? grid_cap(a, (a.n_cut + CW - 1) / CW) : 0;
     if (gs > 0) {
       if (a.kappa == nullptr)
-        inside_kron_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
+        inside_kron_kernel<K, D, T><<<grid_cap(a, (a.n_cut + KronShape<K, D>::CK - 1) / KronShape<K, D>::CK),
+                                      KronShape<K, D>::NTK, 0, s>>>(a, x, v, a.kinfo_cut, a.n_cut, 0);
       else
         kappa_struct_kernel<K, D, T><<<gs, KronShape<K, D>::NT, 0, s>>>(a, x, v, a.kinfo_cut, a.kface_cut, a.n_cut,
                                                                         0);
