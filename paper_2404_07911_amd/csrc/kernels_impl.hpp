@@ -486,6 +486,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 5 
                                                           const int64_t* __restrict__ kface, int n_list,
                                                           int with_volume) {
   constexpr int ND = KronShape<K, D>::ND, NL = KronShape<K, D>::NL, C = KronShape<K, D>::C;
+  // the face loop skips its barriers on wave votes (no lane of the wave has
+  // the face): correct only while a workgroup is one wave
+  static_assert(KronShape<K, D>::NT == 64, "one-wave workgroups");
   __shared__ KappaWork<K, D, T> W;
   const T* __restrict__ tab = a.tab;
   const T* S = tab + TabOff::S(K);
